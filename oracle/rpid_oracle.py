@@ -1,0 +1,278 @@
+"""FP64 CPU oracle for randomized LUPP skeleton selection (ID and CUR).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call
+this module: only the tests, the smoke check and the CPU baseline leg of the
+benchmark use it.  It shares no code with the HIP path.
+
+Follows Dong & Martinsson, "Simpler is better: a comparative study of
+randomized pivoting algorithms for CUR and interpolative decompositions":
+
+* sketch            -- Alg. 2 (Randomized LUPP skeleton selection), step 2:
+                       X = Gamma A with a Gaussian embedding Gamma (Sec. 2.2).
+* lupp_colwise      -- column-wise LU with partial pivoting of Sec. 2.4,
+                       eq. (def_LUPP), Alg. 2 step 3.
+* id_coeffs         -- ID coefficients from the pivoted sketch, Sec. 4:
+                       C^+ A is estimated by X_1^+ X (X_1 = X(:, J_s)).
+* eta               -- the a-posteriori factor of Theorem 1:
+                       eta = || [-X_1^+ X_2 ; I] ||_2 = sqrt(1 + ||Z_rest||_2^2).
+* lupp_rowwise      -- Alg. 2 step 4, row-wise LUPP on C = A(:, J_s).
+* cur_u             -- U = C^+ A R^+ by the stable QR construction of the
+                       Remark "Stable CUR", eq. (cur_stable).
+* residuals         -- relative Frobenius errors of the ID A - C Z, the CUR
+                       A - C U R, the optimal column ID A - C C^+ A (eq.
+                       def_column_id) and the rangefinder A - A X^+ X (Sec. 2.3).
+
+Everything is float64 numpy.  Library primitives used as single steps: matmul,
+QR, triangular/linear solves, SVD (for spectral norms only).
+
+Readings of the paper taken here (the paper is silent or garbled on them):
+* argmax ties go to the smallest original index (eq. def_LUPP gives no rule);
+* the first k pivots of a sketch with l >= k rows depend only on its first k
+  rows (step t reads only row t of the updated sketch), so J_s(k) and Z(k)
+  are computed from X(0:k, :);
+* an exactly zero pivot stops the factorisation: status = t + 1 (1-based
+  step of the zero pivot), k_eff = t (LAPACK getrf "info" convention);
+* the Schur update of eq. (def_LUPP) is the standard one (the printed indices
+  mix t and t + 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+__all__ = [
+    "sketch",
+    "lupp_colwise",
+    "lupp_rowwise",
+    "id_coeffs",
+    "eta",
+    "cur_u",
+    "residuals",
+    "rangefinder_error",
+    "decompose",
+    "NonFiniteInput",
+]
+
+
+class NonFiniteInput(ValueError):
+    """Raised when a matrix handed to the pivoting step holds NaN or Inf."""
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Alg. 2, step 2: row sketch X = Gamma A
+# --------------------------------------------------------------------------
+def sketch(A, Omega):
+    """X = Omega A (l x n) in float64 (Alg. 2, step 2)."""
+    return _f64(Omega) @ _f64(A)
+
+
+# --------------------------------------------------------------------------
+# Sec. 2.4, eq. (def_LUPP): column-wise LU with partial pivoting
+# --------------------------------------------------------------------------
+def lupp_colwise(X, k, gaps=False):
+    """k steps of column-wise LUPP on X (l x n), i.e. getrf of X^T.
+
+    At step t (0-based) the pivot is the remaining column j with the largest
+    |X^(t)(t, j)|; ties go to the smallest j.  The multipliers of step t are
+    X^(t)(t, j) / X^(t)(t, p_t) (the entries of R^LU, all <= 1 in modulus),
+    and the Schur complement update of eq. (def_LUPP) is applied to rows
+    t+1..k-1 of the remaining columns.
+
+    Returns a dict with
+      J      int64[k_eff]  pivots in pivot order (0-based column indices of X)
+      L      (n x k) float64, L[j, t] = multiplier of column j at step t
+             (1 at the pivot's own step, 0 after it) = (R^LU)^T unpermuted
+      U      (k x k) float64, U[t, :] = row t of the updated sketch at the
+             pivot step, restricted to the first k rows (upper triangular
+             as U[t, c] for c >= t holds X^(t)(c, p_t))
+      diag   |U[t, t]|, the pivot magnitudes
+      k_eff, status (0, or t+1 for an exactly zero pivot at step t)
+      gap    (optional) relative gap between the largest and second-largest
+             candidate magnitude at each step
+    """
+    X = _f64(X)
+    l, n = X.shape
+    if not (1 <= k <= min(l, n)):
+        raise ValueError("need 1 <= k <= min(l, n)")
+    if not np.isfinite(X[:k]).all():
+        raise NonFiniteInput("non-finite entry in the sketch")
+    # Work on the transpose: row j of S is column j of X (first k rows).
+    S = X[:k, :].T.copy()
+    remaining = np.ones(n, dtype=bool)
+    J = []
+    L = np.zeros((n, k))
+    U = np.zeros((k, k))
+    gap = []
+    status = 0
+    for t in range(k):
+        cand = np.abs(S[:, t])
+        cand[~remaining] = -1.0
+        p = int(np.argmax(cand))  # first maximum: smallest index among ties
+        piv = S[p, t]
+        if gaps:
+            c2 = cand.copy()
+            c2[p] = -1.0
+            second = c2.max()
+            gap.append((abs(piv) - max(second, 0.0)) / abs(piv) if piv != 0 else 0.0)
+        if piv == 0.0:
+            status = t + 1
+            break
+        J.append(p)
+        # U[c, t] = S[p, c] holds row c of X^(t) at the pivot column for c >= t.
+        U[t, t:] = S[p, t:]
+        remaining[p] = False
+        L[p, t] = 1.0
+        mult = S[remaining, t] / piv
+        L[remaining, t] = mult
+        S[np.ix_(remaining, np.arange(t + 1, k))] -= np.outer(mult, S[p, t + 1 : k])
+    out = dict(
+        J=np.array(J, dtype=np.int64),
+        L=L,
+        U=U,
+        diag=np.abs(np.diag(U)),
+        k_eff=len(J),
+        status=status,
+    )
+    if gaps:
+        out["gap"] = np.array(gap)
+    return out
+
+
+def lupp_rowwise(C, k, gaps=False):
+    """k steps of row-wise LUPP on C (m x k'), i.e. column-wise LUPP on C^T
+    (Alg. 2, step 4).  Pivots are row indices of C."""
+    return lupp_colwise(_f64(C).T, k, gaps=gaps)
+
+
+# --------------------------------------------------------------------------
+# Sec. 4: ID coefficients from the pivoted sketch, and Theorem 1's eta
+# --------------------------------------------------------------------------
+def id_coeffs(X, J, k=None):
+    """Z (k x n) with A ~ A(:, J) Z, estimated from the sketch: Z = X_1^{-1} X_k
+    where X_k = X(0:k, :) and X_1 = X_k(:, J) (Sec. 4).  Z(:, J) = I exactly."""
+    X = _f64(X)
+    J = np.asarray(J, dtype=np.int64)
+    if k is None:
+        k = J.shape[0]
+    J = J[:k]
+    Xk = X[:k, :]
+    Z = np.linalg.solve(Xk[:, J], Xk)
+    Z[:, J] = np.eye(k)
+    return Z
+
+
+def rest_of(n, J):
+    mask = np.ones(n, dtype=bool)
+    mask[np.asarray(J, dtype=np.int64)] = False
+    return np.nonzero(mask)[0]
+
+
+def eta(Z, J):
+    """Theorem 1: eta = ||[-X_1^+ X_2; I]||_2 = sqrt(1 + ||Z_rest||_2^2)."""
+    Z = _f64(Z)
+    rest = rest_of(Z.shape[1], J)
+    if rest.size == 0:
+        return 1.0
+    s = np.linalg.norm(Z[:, rest], 2)
+    return float(np.sqrt(1.0 + s * s))
+
+
+# --------------------------------------------------------------------------
+# Remark "Stable CUR": U = C^+ A R^+ through unpivoted QR of C and R^T
+# --------------------------------------------------------------------------
+def cur_u(A, J, I):
+    """U (k x k) such that C U R = Q_C (Q_C^T A Q_R) Q_R^T (eq. cur_stable)."""
+    A = _f64(A)
+    C = A[:, J]
+    R = A[I, :]
+    qc, rc = np.linalg.qr(C)
+    qr_, rr = np.linalg.qr(R.T)
+    M = qc.T @ A @ qr_
+    # U = R_C^{-1} M R_R^{-T}
+    U = sla.solve_triangular(rc, M, lower=False)
+    U = sla.solve_triangular(rr, U.T, lower=False).T
+    return U
+
+
+# --------------------------------------------------------------------------
+# Error metrics
+# --------------------------------------------------------------------------
+def _fro(a):
+    return float(np.sqrt(np.sum(np.square(a))))
+
+
+def rangefinder_error(A, X, k, ord="fro"):
+    """||A - A X_k^+ X_k|| / ||A|| (Sec. 2.3), X_k = X(0:k, :)."""
+    A = _f64(A)
+    q, _ = np.linalg.qr(_f64(X)[:k, :].T)
+    E = A - (A @ q) @ q.T
+    if ord == "fro":
+        return _fro(E) / _fro(A)
+    return float(np.linalg.norm(E, 2) / np.linalg.norm(A, 2))
+
+
+def residuals(A, J, Z=None, I=None, U=None, ord="fro"):
+    """Relative errors; explicit differences (never an expanded form).
+
+    id    ||A - A(:,J) Z|| / ||A||          (Z from the sketch, Sec. 4)
+    idopt ||A - C C^+ A|| / ||A||           (eq. def_column_id)
+    cur   ||A - C U R|| / ||A||             (eq. def_cur)
+    rowopt||A - A R^+ R|| / ||A||           (eq. def_row_id)
+    """
+    A = _f64(A)
+    nrm = (lambda e: _fro(e)) if ord == "fro" else (lambda e: float(np.linalg.norm(e, 2)))
+    na = nrm(A)
+    C = A[:, J]
+    out = {}
+    qc, _ = np.linalg.qr(C)
+    out["idopt"] = nrm(A - qc @ (qc.T @ A)) / na
+    if Z is not None:
+        out["id"] = nrm(A - C @ _f64(Z)) / na
+    if I is not None:
+        R = A[I, :]
+        qr_, _ = np.linalg.qr(R.T)
+        out["rowopt"] = nrm(A - (A @ qr_) @ qr_.T) / na
+        if U is not None:
+            out["cur"] = nrm(A - (C @ _f64(U)) @ R) / na
+    return out
+
+
+def optimal_error(s, k):
+    """||A - A_k||_F / ||A||_F from the singular values s (Eckart-Young)."""
+    s = np.asarray(s, dtype=np.float64)
+    return float(np.sqrt(np.sum(s[k:] ** 2) / np.sum(s**2)))
+
+
+# --------------------------------------------------------------------------
+# The whole path of Alg. 2 with the sketch-based ID and stable CUR
+# --------------------------------------------------------------------------
+def decompose(A, Omega, k, gaps=False, want_cur=True):
+    """Alg. 2 end to end: X = Omega A; LUPP on X -> J; Z; C = A(:, J);
+    LUPP on C -> I; U.  Returns a dict with every intermediate."""
+    A = _f64(A)
+    X = sketch(A, Omega)
+    col = lupp_colwise(X, k, gaps=gaps)
+    out = dict(X=X, J=col["J"], L=col["L"], Ufac=col["U"], diag=col["diag"],
+               k_eff=col["k_eff"], status=col["status"])
+    if gaps:
+        out["gap_J"] = col["gap"]
+    if col["status"] != 0:
+        return out
+    J = col["J"]
+    Z = id_coeffs(X, J, k)
+    out["Z"] = Z
+    out["eta"] = eta(Z, J)
+    if want_cur:
+        C = A[:, J]
+        row = lupp_rowwise(C, k, gaps=gaps)
+        out["I"] = row["J"]
+        out["status_I"] = row["status"]
+        if gaps:
+            out["gap_I"] = row["gap"]
+        if row["status"] == 0:
+            out["U"] = cur_u(A, J, row["J"])
+    return out

@@ -1,0 +1,187 @@
+"""Seeded synthetic inputs for randomized LUPP skeleton selection.
+
+This module only builds test matrices and Gaussian embeddings; it holds none
+of the method's arithmetic.  Both the FP64 oracle (through the tests) and the
+HIP path take their inputs from here, so the two see identical values.
+
+Matrices are returned column-major: a numpy array in Fortran order, or a torch
+tensor ``t`` whose transpose ``t.T`` is contiguous (``t.stride() == (1, m)``).
+
+Workload recipes (the paper's own datasets are not used; these synthetic
+matrices stand in for them, with spectra controlled exactly):
+
+* ``spectral``: A = U diag(s) V^T with U, V Haar-distributed orthonormal
+  factors (QR of a Gaussian matrix with the sign of diag(R) folded in).
+* ``lowrank_noise``: A = F G + sigma N, F, G Gaussian factors.
+* ``nonneg_lowrank``: A = |F| |G| + uniform noise (non-negative entries).
+* ``gaussian_embedding``: Omega with iid N(0, 1) entries (the embedding of
+  Section 2.2 with mean 0; the scale does not change the pivots).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Workload shapes: (m, n, k, l).
+WORKLOADS = {
+    "exp1000x800": dict(m=1000, n=800, k=50, l=50),
+    "poly8192": dict(m=8192, n=8192, k=256, l=272),
+    "lowrank16384_bf16": dict(m=16384, n=16384, k=512, l=544),
+    "nonneg65536x4096_fp8": dict(m=65536, n=4096, k=384, l=400),
+}
+
+STREAM_U, STREAM_V, STREAM_OMEGA, STREAM_NOISE = 0, 1, 2, 3
+
+
+def rng_for(case: int, rep: int, stream: int) -> np.random.Generator:
+    """Independent PCG64 stream for (case, repetition, stream)."""
+    return np.random.default_rng([1000 * case + rep, stream])
+
+
+def haar(rng: np.random.Generator, m: int, r: int) -> np.ndarray:
+    """m x r matrix with orthonormal columns, Haar distributed (Mezzadri)."""
+    g = rng.standard_normal((m, r))
+    q, rr = np.linalg.qr(g)
+    d = np.sign(np.diag(rr))
+    d[d == 0] = 1.0
+    return q * d
+
+
+def spectral(m: int, n: int, s: np.ndarray, rng_u, rng_v) -> np.ndarray:
+    """A = U diag(s) V^T, float64, Fortran order; len(s) <= min(m, n)."""
+    s = np.asarray(s, dtype=np.float64)
+    r = s.shape[0]
+    u = haar(rng_u, m, r)
+    v = haar(rng_v, n, r)
+    return np.asfortranarray((u * s) @ v.T)
+
+
+def exp_spectrum(r: int, decades: float = 8.0) -> np.ndarray:
+    """s_i = 10^(-decades (i-1)/(r-1)), i = 1..r."""
+    i = np.arange(r, dtype=np.float64)
+    return 10.0 ** (-decades * i / (r - 1))
+
+
+def poly_spectrum(r: int, power: float = 2.0) -> np.ndarray:
+    """s_i = i^(-power), i = 1..r."""
+    return np.arange(1, r + 1, dtype=np.float64) ** (-power)
+
+
+def gaussian_embedding(rng: np.random.Generator, l: int, m: int) -> np.ndarray:
+    """l x m iid N(0, 1), float64, Fortran order."""
+    return np.asfortranarray(rng.standard_normal((l, m)))
+
+
+def lowrank_noise(rng_f, rng_g, rng_e, m, n, r, noise) -> np.ndarray:
+    """F (m x r) G (r x n) + noise * N(0,1), float64, Fortran order."""
+    f = rng_f.standard_normal((m, r))
+    g = rng_g.standard_normal((r, n))
+    a = f @ g
+    a += noise * rng_e.standard_normal((m, n))
+    return np.asfortranarray(a)
+
+
+def nonneg_lowrank(rng_f, rng_g, rng_e, m, n, r, noise) -> np.ndarray:
+    """|F| |G| + uniform[0, noise], float64, Fortran order."""
+    f = np.abs(rng_f.standard_normal((m, r)))
+    g = np.abs(rng_g.standard_normal((r, n)))
+    a = f @ g
+    a += noise * rng_e.random((m, n))
+    return np.asfortranarray(a)
+
+
+def case_exp1000x800(rep: int = 0):
+    """1000 x 800, Haar U (1000 x 800) and V (800 x 800), exponential
+    spectrum over 8 decades; k = l = 50; Omega 50 x 1000 N(0, 1)."""
+    w = WORKLOADS["exp1000x800"]
+    s = exp_spectrum(800, 8.0)
+    a = spectral(w["m"], w["n"], s, rng_for(0, rep, STREAM_U), rng_for(0, rep, STREAM_V))
+    om = gaussian_embedding(rng_for(0, rep, STREAM_OMEGA), w["l"], w["m"])
+    return a, om, w["k"], w["l"]
+
+
+def small_spectral_case(m, n, k, l, s, seed):
+    """Any small spectral case: (A, Omega) float64 Fortran order."""
+    a = spectral(m, n, s, rng_for(seed, 0, STREAM_U), rng_for(seed, 0, STREAM_V))
+    om = gaussian_embedding(rng_for(seed, 0, STREAM_OMEGA), l, m)
+    return a, om
+
+
+# --------------------------------------------------------------------------
+# Device-side generation (torch) for the large workloads.  Values come from
+# torch's own generator; the oracle receives the very same values by copying
+# the generated tensors back to the host.
+# --------------------------------------------------------------------------
+def _torch():
+    import torch  # noqa: PLC0415
+
+    return torch
+
+
+def torch_colmajor(a_np, dtype, device):
+    """Copy a Fortran-order numpy matrix into a column-major torch tensor."""
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(a_np).T)).to(device=device, dtype=dtype)
+    return t.T
+
+
+def empty_colmajor(rows, cols, dtype, device):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype, device=device).T
+
+
+def torch_haar(gen, m, r, device):
+    torch = _torch()
+    g = torch.randn((m, r), generator=gen, dtype=torch.float64, device=device)
+    q, rr = torch.linalg.qr(g)
+    d = torch.sign(torch.diagonal(rr))
+    d[d == 0] = 1.0
+    return q * d
+
+
+def torch_spectral(m, n, s, seed, device):
+    """A = U diag(s) V^T in float64 on ``device``, column-major."""
+    torch = _torch()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    s_t = torch.as_tensor(np.asarray(s, dtype=np.float64), device=device)
+    r = s_t.shape[0]
+    u = torch_haar(gen, m, r, device)
+    v = torch_haar(gen, n, r, device)
+    # column-major result: build A^T (n x m) contiguous, return its transpose
+    at = (v * s_t) @ u.T
+    return at.T
+
+
+def torch_gaussian(rows, cols, seed, device, dtype=None):
+    """rows x cols iid N(0,1), column-major, float64 unless dtype given."""
+    torch = _torch()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    t = torch.randn((cols, rows), generator=gen, dtype=torch.float64, device=device)
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.T
+
+
+def torch_lowrank_noise(m, n, r, noise, seed, device):
+    """F G + noise N(0,1) in float32, column-major (rank-r Gaussian factors)."""
+    torch = _torch()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f = torch.randn((m, r), generator=gen, dtype=torch.float32, device=device)
+    g = torch.randn((r, n), generator=gen, dtype=torch.float32, device=device)
+    at = (f @ g).T.contiguous()
+    at += noise * torch.randn((n, m), generator=gen, dtype=torch.float32, device=device)
+    return at.T
+
+
+def torch_nonneg_lowrank(m, n, r, noise, seed, device):
+    """|F| |G| + uniform[0, noise] in float32, column-major."""
+    torch = _torch()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f = torch.randn((m, r), generator=gen, dtype=torch.float32, device=device).abs_()
+    g = torch.randn((r, n), generator=gen, dtype=torch.float32, device=device).abs_()
+    at = (f @ g).T.contiguous()
+    at += noise * torch.rand((n, m), generator=gen, dtype=torch.float32, device=device)
+    return at.T

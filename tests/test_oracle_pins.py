@@ -1,0 +1,72 @@
+"""The FP64 oracle against what the paper and the mathematics fix (CPU)."""
+import types
+
+import numpy as np
+import pytest
+
+import oracle.rpid_oracle as O
+from tests import oracle_pins as P
+
+
+@pytest.mark.parametrize("pin", P.ALL_PINS, ids=lambda f: f.__name__)
+def test_pin(pin):
+    pin(O)
+
+
+def test_nonfinite_rejected():
+    X = np.ones((3, 5))
+    X[1, 2] = np.nan
+    with pytest.raises(O.NonFiniteInput):
+        O.lupp_colwise(X, 3)
+
+
+def test_exp1000x800_floor():
+    """The exponential workload's optimal rank-50 relative error is a closed
+    form of its spectrum (Eckart-Young); the oracle's optimal-ID and sketch-ID
+    errors sit at or above it, and the generator realises the spectrum."""
+    from paper_2104_05877_amd import inputs
+
+    s = inputs.exp_spectrum(800, 8.0)
+    assert abs(O.optimal_error(s, 50) - 0.3158) < 5e-5
+    a, om, k, l = inputs.case_exp1000x800()
+    sv = np.linalg.svd(a, compute_uv=False)
+    np.testing.assert_allclose(sv, s, rtol=1e-9, atol=1e-15)
+    d = O.decompose(a, om, k)
+    r = O.residuals(a, d["J"], Z=d["Z"], I=d["I"], U=d["U"])
+    assert O.optimal_error(s, k) <= r["idopt"] <= r["id"]
+    assert r["idopt"] <= r["cur"]
+
+
+MUTANTS = {
+    "argmax without modulus": ("cand = np.abs(S[:, t])", "cand = S[:, t].copy()"),
+    "Schur update sign": ("-= np.outer(mult, S[p, t + 1 : k])", "+= np.outer(mult, S[p, t + 1 : k])"),
+    "ties to largest index": ("p = int(np.argmax(cand))", "p = int(len(cand) - 1 - np.argmax(cand[::-1]))"),
+    "multiplier from wrong pivot": ("mult = S[remaining, t] / piv", "mult = S[remaining, t] / S[p, min(t + 1, k - 1)]"),
+    "U row stored as column": ("U[t, t:] = S[p, t:]", "U[t:, t] = S[p, t:]"),
+    "Z with transposed X_1": ("Z = np.linalg.solve(Xk[:, J], Xk)", "Z = np.linalg.solve(Xk[:, J].T, Xk)"),
+    "U right factor on the left": (
+        "U = sla.solve_triangular(rr, U.T, lower=False).T",
+        "U = sla.solve_triangular(rr, U, lower=False)",
+    ),
+    "eta without the identity block": ("return float(np.sqrt(1.0 + s * s))", "return float(np.sqrt(s * s))"),
+    "id residual not relative": ('out["id"] = nrm(A - C @ _f64(Z)) / na', 'out["id"] = nrm(A - C @ _f64(Z))'),
+    "CUR with R transposed factor": ('qr_, rr = np.linalg.qr(R.T)', 'qr_, rr = np.linalg.qr(R.T[:, ::-1])'),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_oracle_mutants_are_caught(name):
+    """A plausible mistake planted in the oracle (on the CPU) fails a pin."""
+    old, new = MUTANTS[name]
+    src = open(O.__file__).read()
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("oracle_mutant")
+    exec(compile(src.replace(old, new), "oracle_mutant", "exec"), mod.__dict__)
+    caught = []
+    for pin in P.ALL_PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin(mod)
+        except Exception as e:  # noqa: BLE001  (assertion or numerical failure)
+            caught.append((pin.__name__, type(e).__name__))
+    assert caught, f"no pin catches mutant {name!r}"
