@@ -1,0 +1,207 @@
+/*
+ * rpid.h -- C-ABI of the MI355X (gfx950) library for randomized LUPP skeleton
+ * selection: interpolative (ID) and CUR decompositions.
+ *
+ * Method: Dong & Martinsson, "Simpler is better: a comparative study of
+ * randomized pivoting algorithms for CUR and interpolative decompositions",
+ * Alg. 2 (Randomized LUPP skeleton selection) with the sketch-based ID
+ * coefficients of Sec. 4 and the stable CUR construction of the Remark
+ * "Stable CUR" (eq. cur_stable).
+ *
+ * Conventions (all entry points):
+ *  - Matrices are DEVICE pointers, column-major, with a leading dimension
+ *    ld >= number of rows.  Element type is given by an rpid_dtype argument.
+ *  - Index vectors (J_s, I_s) are DEVICE int64 arrays, 0-based, in pivot
+ *    order (the paper's MATLAB indices are 1-based).
+ *  - Host scalars (k_eff, eta, rel_fro) are HOST pointers; a call that
+ *    receives a non-NULL host scalar synchronises the context's stream
+ *    before returning.  Calls with no host scalar only enqueue work.
+ *  - The caller allocates and owns every input and output buffer.  The
+ *    context owns a device workspace, grown on demand (hipMalloc) and freed
+ *    by rpid_destroy.  No pointer passed in is retained after a call.
+ *  - All work is enqueued on the context's HIP stream.  A context is used by
+ *    one host thread at a time.
+ *  - Return value: RPID_OK (0); a negative value -i when the i-th argument
+ *    (1-based, the context counting as argument 1) is invalid; one of the
+ *    RPID_ERR_* codes; or a positive value t+1 when the pivot of 0-based
+ *    step t is exactly zero (rank deficiency, the premise of Lemma 1
+ *    violated), in which case *k_eff = t and only the first t pivots are
+ *    defined (LAPACK getrf "info" convention).
+ */
+#ifndef RPID_H
+#define RPID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPID_F64 = 0,      /* IEEE binary64 */
+  RPID_F32 = 1,      /* IEEE binary32 */
+  RPID_BF16 = 2,     /* bfloat16 (8-bit exponent, 7-bit mantissa) */
+  RPID_FP8_E4M3 = 3  /* OCP FP8 E4M3 (max 448, no infinities) */
+} rpid_dtype;
+
+typedef enum { RPID_RESIDUAL_ID = 0, RPID_RESIDUAL_CUR = 1 } rpid_residual_kind;
+
+#define RPID_OK 0
+#define RPID_ERR_NONFINITE (-100)   /* NaN/Inf in a matrix handed to pivoting */
+#define RPID_ERR_HIP (-101)         /* a HIP runtime call failed */
+#define RPID_ERR_NOMEM (-102)       /* workspace allocation failed */
+#define RPID_ERR_UNSUPPORTED (-103) /* dtype combination or size not supported */
+#define RPID_ERR_LAUNCH (-104)      /* cooperative launch could not co-schedule the grid */
+#define RPID_ERR_TIMEOUT (-105)     /* a device-side wait exceeded its spin limit */
+#define RPID_ERR_BREAKDOWN (-106)   /* Cholesky breakdown while orthonormalising C or R^T */
+
+typedef struct rpid_ctx_s* rpid_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+int rpid_create(rpid_ctx* out, int device, void* hip_stream);
+/* Free the workspace and the context (synchronises its stream first). */
+int rpid_destroy(rpid_ctx ctx);
+/* Change the stream later calls enqueue on. */
+int rpid_set_stream(rpid_ctx ctx, void* hip_stream);
+/* Static description of a status code. */
+const char* rpid_status_string(int status);
+/* Library ABI version (increments on any signature change). */
+int rpid_version(void);
+
+/*
+ * S2 -- row sketch X = Omega A (Alg. 2, step 2; the Gaussian embedding of
+ * Sec. 2.2, drawn by the caller so that any reference sees the same values).
+ *   A      m x n, lda >= m, type a_t
+ *   Omega  l x m, ldo >= l, type o_t
+ *   X      l x n, ldx >= l, type x_t (output)
+ * Supported (a_t, o_t, x_t): (F64,F64,F64) on FP64 MFMA, (F32,F32,F32) on
+ * FP32 MFMA, (BF16,BF16,F32) on BF16 MFMA with FP32 accumulation.
+ * 1 <= l <= 1024.
+ */
+int rpid_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo, void* X, rpid_dtype x_t,
+                int64_t ldx);
+
+/*
+ * S2, FP8 form -- X = Omega A with A and Omega quantised to OCP E4M3 with
+ * power-of-two scales, multiplied on FP8 MFMA with FP32 accumulation, and
+ * the scales undone exactly in X:
+ *   A_q(:, j) = e4m3(A(:, j) * 2^ea[j]),  ea[j] = floor(log2(448 / max|A(:, j)|))
+ *   Om_q      = e4m3(Omega * 2^eo),       eo    = floor(log2(448 / max|Omega|))
+ *   X(:, j)   = (Om_q A_q(:, j)) * 2^-(eo + ea[j])
+ * (e4m3 rounds to nearest even and saturates at +-448.)  A is F32 (m x n),
+ * Omega F32 (l x m), X F32 (l x n).  A column of zeros gets ea[j] = 0.
+ */
+int rpid_sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                    const float* Omega, int64_t l, int64_t ldo, float* X, int64_t ldx);
+
+/*
+ * S3 -- column-wise LU with partial pivoting of the sketch (Alg. 2, step 3;
+ * eq. def_LUPP), k steps, i.e. getrf of the n x k panel X(0:k, :)^T.
+ * Step t picks the remaining column j with the largest |X^(t)(t, j)|; ties
+ * go to the smallest j.  Only the first k rows of X are read (the first k
+ * pivots depend on nothing else).
+ *   X      l x n, ldx >= l, type x_t in {F64, F32}; the factorisation runs
+ *          in x_t arithmetic
+ *   k      1 <= k <= min(l, n), k <= 1024
+ *   J      int64[k]   pivots in pivot order (0-based columns of X)
+ *   Lf     n x k, ldl >= n, type x_t: Lf(j, t) = multiplier of column j at
+ *          step t (|.| <= 1), 1 at its own pivot step, 0 after it
+ *   Uf     k x k, ldu >= k, type x_t: upper triangular, Uf(t, c) = row c of
+ *          the updated sketch at pivot p_t (zero below the diagonal); then
+ *          X(0:k, :)^T = Lf Uf up to rounding
+ *   diagU  k values of type x_t: |Uf(t, t)| (pivot magnitudes); may be NULL
+ *   k_eff  host int64*, NULL to skip the synchronising status read
+ * Returns RPID_ERR_NONFINITE if the panel holds NaN/Inf (nothing defined).
+ */
+int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                        int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
+                        int64_t ldu, void* diagU, int64_t* k_eff);
+
+/*
+ * S4 -- ID coefficients from the pivoted sketch (Sec. 4: C^+ A ~ X_1^+ X):
+ * Z = X_1^{-1} X_k with X_k = X(0:k, :), X_1 = X_k(:, J), so that A ~ A(:, J) Z.
+ * Computed from the LUPP factors: Z(:, J[t]) = e_t and, for j not in J,
+ * Z(:, j) solves Lf(J, :)^T z = Lf(j, :)^T (unit upper triangular).
+ * With refine_steps = 1, one step of iterative refinement in FP64 follows:
+ * r = X_k(:, j) - X_1 z (X promoted to FP64), X_1 d = r solved through the
+ * factors (Uf^T then Lf(J,:)^T), z += d.
+ *   X, x_t, l, n, ldx, k, J, Lf, ldl, Uf, ldu as returned for rpid_select_columns
+ *   Z      k x n FP64, ldz >= k (output)
+ *   eta    host double*, NULL to skip: Theorem 1's a-posteriori factor
+ *          sqrt(1 + ||Z_rest||_2^2), Z_rest = Z without the columns J
+ *          (spectral norm by power iteration on Z_rest Z_rest^T to 1e-10
+ *          relative change or 500 iterations)
+ */
+int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                   int64_t ldx, int64_t k, const int64_t* J, const void* Lf, int64_t ldl,
+                   const void* Uf, int64_t ldu, double* Z, int64_t ldz, int refine_steps,
+                   double* eta);
+
+/*
+ * S5-S7 -- CUR from the column skeleton (Alg. 2, step 4; eq. def_cur with
+ * the stable construction eq. cur_stable):
+ *   C = A(:, J) (pivot order); row-wise LUPP on C (k steps; ties to the
+ *   smallest row; FP64 arithmetic if a_t = F64, else FP32) gives I;
+ *   R = A(I, :); C = Q_C R_C, R^T = Q_R R_R (orthonormal Q by shifted
+ *   Cholesky-QR in FP64); U = R_C^{-1} (Q_C^T A Q_R) R_R^{-T} in FP64, so
+ *   that C U R = Q_C (Q_C^T A Q_R) Q_R^T.
+ *   A      m x n, lda >= m, a_t in {F64, F32, BF16}
+ *   J      int64[k] from rpid_select_columns (k <= 1024, k <= min(m, n))
+ *   I      int64[k] (output)
+ *   U      k x k FP64, ldu >= k (output)
+ *   k_eff  host int64*, NULL to skip: rank reached by the row LUPP
+ */
+int rpid_cur(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+             int64_t k, const int64_t* J, int64_t* I, double* U, int64_t ldu, int64_t* k_eff);
+
+/*
+ * S8 -- relative Frobenius error of the decomposition, by explicit
+ * differences (the error measure of the experiments of Sec. 5):
+ *   RPID_RESIDUAL_ID : ||A - A(:, J) Z||_F / ||A||_F   (uses J, Z)
+ *   RPID_RESIDUAL_CUR: ||A - A(:, J) U A(I, :)||_F / ||A||_F (uses J, I, U)
+ * A is m x n of type a_t in {F64, F32, BF16}; Z is k x n FP64 (ldz), U is
+ * k x k FP64 (ldu); unused arguments may be NULL.  The products run in FP64
+ * for F64/F32 storage; for BF16 storage on BF16 MFMA with the FP64 factor
+ * split into three BF16 terms and FP32 accumulation.  Sums of squares are
+ * accumulated in FP64.  *rel_fro (host) receives the ratio; synchronises.
+ */
+int rpid_residual(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                  int64_t lda, int64_t k, const int64_t* J, const double* Z, int64_t ldz,
+                  const int64_t* I, const double* U, int64_t ldu, double* rel_fro);
+
+/*
+ * Learned rank (not in the paper).  Features of the pivot-magnitude profile
+ * of a sketch's LUPP: f_t = max(log10(diagU[t] / diagU[0]), -20), t < L;
+ * entries t >= k_eff (zero pivots) are -20.  diagU is type x_t (F32/F64),
+ * feats is F32[L].
+ */
+int rpid_mlp_features(rpid_ctx ctx, const void* diagU, rpid_dtype x_t, int64_t L, int64_t k_eff,
+                      float* feats);
+
+/*
+ * MLP 512 -> 128 -> 128 -> 1 (FP32, ReLU on the two hidden layers).
+ * W is one flat device buffer of RPID_MLP_NPARAM floats:
+ *   W1 (128 x 512, row-major), b1 (128), W2 (128 x 128), b2 (128), w3 (128), b3 (1).
+ * forward : yhat[B] = net(feats[B x 512], row-major); act (nullable) receives
+ *           the hidden activations needed by backward, B x 256 floats.
+ * backward: dW = d(sum_b dy[b] * yhat[b]) / dW, accumulated over the batch
+ *           (overwrites dW).
+ * adam    : one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at step t >= 1.
+ */
+#define RPID_MLP_IN 512
+#define RPID_MLP_H 128
+#define RPID_MLP_NPARAM (128 * 512 + 128 + 128 * 128 + 128 + 128 + 1)
+int rpid_mlp_forward(rpid_ctx ctx, const float* W, const float* feats, int64_t B, float* yhat,
+                     float* act);
+int rpid_mlp_backward(rpid_ctx ctx, const float* W, const float* feats, const float* act,
+                      const float* dy, int64_t B, float* dW);
+int rpid_mlp_adam(rpid_ctx ctx, float* W, const float* dW, float* m1, float* m2, float lr,
+                  int64_t t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPID_H */

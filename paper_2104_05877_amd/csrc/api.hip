@@ -1,0 +1,648 @@
+// C-ABI entry points of librpid (declared in include/rpid.h): argument
+// validation, workspace sizing and the order of the kernels of each step.
+#include <algorithm>
+#include <new>
+
+#include "rpid_internal.hpp"
+
+namespace rpid {
+
+template <typename TA>
+int residual_f64(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const TA* A, int64_t lda,
+                 const double* P, int64_t ldp, const double* Q, int64_t ldq, double* partials,
+                 double* out2);
+int residual_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* A, int64_t lda,
+                  const uint16_t* P, int64_t ldp, const uint16_t* Q, int64_t ldq,
+                  double* partials, double* out2);
+size_t residual_partials(int64_t m, int64_t n, bool bf16);
+int mlp_forward(rpid_ctx, const float*, const float*, int64_t, float*, float*);
+int mlp_backward(rpid_ctx, const float*, const float*, const float*, const float*, int64_t,
+                 float*, size_t);
+int mlp_adam(rpid_ctx, float*, const float*, float*, float*, float, int64_t);
+int mlp_features(rpid_ctx, const void*, bool, int64_t, int64_t, float*);
+size_t mlp_backward_workspace(int64_t B);
+int sketch_fp8(rpid_ctx, const float*, int64_t, int64_t, int64_t, const float*, int64_t, int64_t,
+               float*, int64_t, size_t);
+size_t sketch_fp8_workspace(int64_t m, int64_t n, int64_t l);
+
+int ensure_workspace(rpid_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return RPID_OK;
+  if (ctx->ws) {
+    RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    RPID_HIP_CHECK(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 4 + (1u << 20);
+  if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+    ctx->ws = nullptr;
+    return RPID_ERR_NOMEM;
+  }
+  ctx->ws_bytes = want;
+  return RPID_OK;
+}
+
+static int read_status(rpid_ctx ctx, const int64_t* status_dev, int64_t* out) {
+  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+  RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  *out = *ctx->host_status;
+  return RPID_OK;
+}
+
+static int read_doubles(rpid_ctx ctx, const double* dev, double* host, int count) {
+  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, dev, sizeof(double) * count,
+                                hipMemcpyDeviceToHost, ctx->stream));
+  RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < count; ++i) host[i] = reinterpret_cast<double*>(ctx->host_status)[i];
+  return RPID_OK;
+}
+
+static bool is_lupp_type(rpid_dtype t) { return t == RPID_F64 || t == RPID_F32; }
+static size_t esize(rpid_dtype t) {
+  switch (t) {
+    case RPID_F64: return 8;
+    case RPID_F32: return 4;
+    case RPID_BF16: return 2;
+    case RPID_FP8_E4M3: return 1;
+  }
+  return 0;
+}
+
+// Transpose-copy for the packing of Omega (element size 2, 4 or 8 bytes).
+template <typename E>
+__global__ void transpose_copy_kernel(int64_t rows, int64_t cols, const E* X, int64_t ldx, E* Y,
+                                      int64_t ldy) {
+  __shared__ E tile[32][33];
+  const int64_t bi = (int64_t)blockIdx.x * 32, bj = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi + tx, j = bj + r;
+    if (i < rows && j < cols) tile[r][tx] = X[i + j * ldx];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = bj + tx, i = bi + r;
+    if (i < rows && j < cols) Y[j + i * ldy] = tile[tx][r];
+  }
+}
+
+template <typename E>
+static int transpose_copy(rpid_ctx ctx, int64_t rows, int64_t cols, const E* X, int64_t ldx, E* Y,
+                          int64_t ldy) {
+  dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32));
+  hipLaunchKernelGGL((transpose_copy_kernel<E>), grid, dim3(256), 0, ctx->stream, rows, cols, X,
+                     ldx, Y, ldy);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+
+// W(0:k, :) += W(k:2k, :) (the two BF16 terms of a split left operand),
+// written as FP64 into Wd (k x n).
+__global__ void sum_halves_kernel(int64_t k, int64_t n, const float* W2, double* Wd) {
+  const int64_t total = k * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % k, j = e / k;
+    Wd[i + j * k] = (double)W2[i + j * 2 * k] + (double)W2[i + k + j * 2 * k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CUR: shifted/plain Cholesky-QR2 of C (m x k) and R^T (n x k), both FP64,
+// batched.  On return Q_C overwrites C64, Q_R overwrites Rt64, and the
+// factors R_C = R2c R1c, R_R = R2r R1r are left in F (4 k x k matrices:
+// R1c, R1r, R2c, R2r).
+// ---------------------------------------------------------------------------
+static int chol_qr_pass(rpid_ctx ctx, int64_t m, int64_t n, int64_t k, double* C64,
+                        double* Rt64, double* F1c, double* F1r, int64_t* status_dev, double shift,
+                        size_t ws_tmp) {
+  // Gram matrices into F1c / F1r (adjacent: stride k*k)
+  RPID_CHECK(dgemm(ctx, true, false, k, k, m, 1.0, C64, m, C64, m, 0.0, F1c, k, ws_tmp));
+  RPID_CHECK(dgemm(ctx, true, false, k, k, n, 1.0, Rt64, n, Rt64, n, 0.0, F1r, k, ws_tmp));
+  if (shift > 0.0) {
+    RPID_CHECK(add_trace_shift(ctx, k, F1c, k, shift));
+    RPID_CHECK(add_trace_shift(ctx, k, F1r, k, shift));
+  }
+  RPID_CHECK(cholesky_batched(ctx, 2, k, F1c, k, F1r - F1c, status_dev));
+  // Q = X R^{-1}: each row x of X solves R^T q = x
+  RPID_CHECK(tri_solve<double>(ctx, k, m, F1c, k, true, true, false, C64, m, 1, C64, m, 1));
+  RPID_CHECK(tri_solve<double>(ctx, k, n, F1r, k, true, true, false, Rt64, n, 1, Rt64, n, 1));
+  return RPID_OK;
+}
+
+// ---------------------------------------------------------------------------
+template <typename TA>
+static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                    int64_t k, const int64_t* J, int64_t* I, double* U, int64_t ldu,
+                    int64_t* k_eff) {
+  const bool f64 = a_t == RPID_F64;
+  Carve cv;
+  const size_t o_status = cv.take<int64_t>(8);
+  const size_t o_C64 = cv.take<double>((size_t)m * k);
+  const size_t o_C32 = f64 ? 0 : cv.take<float>((size_t)m * k);
+  const size_t o_Lc = cv.take<double>((size_t)m * k);  // LUPP multipliers (discarded)
+  const size_t o_Uc = cv.take<double>((size_t)k * k);
+  const size_t o_Rt = cv.take<double>((size_t)n * k);
+  const size_t o_F = cv.take<double>((size_t)4 * k * k);
+  const size_t o_W = cv.take<double>((size_t)k * n);
+  const size_t o_W2 = cv.take<float>((size_t)2 * k * n);
+  const size_t o_Pt = cv.take<char>((size_t)m * 2 * k * 4);
+  const size_t o_M = cv.take<double>((size_t)k * k);
+  const size_t o_tmp = cv.off;
+  const size_t tmp_bytes =
+      std::max(lupp_workspace_bytes(ctx, m, k, f64 ? 8 : 4),
+               std::max(sketch_workspace_bytes(ctx, m, n, 2 * k, 8),
+                        (size_t)64 * k * k * sizeof(double) + 4096));
+  RPID_CHECK(ensure_workspace(ctx, o_tmp + tmp_bytes));
+  int64_t* status_dev = ws_ptr<int64_t>(ctx, o_status);
+  double* C64 = ws_ptr<double>(ctx, o_C64);
+  double* Rt = ws_ptr<double>(ctx, o_Rt);
+  double* F = ws_ptr<double>(ctx, o_F);
+  const int64_t kk = k * k;
+
+  // (S5) C = A(:, J); (S6) row-wise LUPP on C gives I
+  RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(I), (size_t)k, 0ull));
+  RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, C64, m));
+  if (f64) {
+    RPID_CHECK(lupp_panel<double>(ctx, C64, 1, m, m, k, I, ws_ptr<double>(ctx, o_Lc), m,
+                                  ws_ptr<double>(ctx, o_Uc), k, nullptr, o_tmp, status_dev));
+  } else {
+    float* C32 = ws_ptr<float>(ctx, o_C32);
+    RPID_CHECK(gather_columns<TA, float>(ctx, m, k, A, lda, n, J, C32, m));
+    RPID_CHECK(lupp_panel<float>(ctx, C32, 1, m, m, k, I, ws_ptr<float>(ctx, o_Lc), m,
+                                 ws_ptr<float>(ctx, o_Uc), k, nullptr, o_tmp, status_dev));
+  }
+  int64_t st = 0;
+  RPID_CHECK(read_status(ctx, status_dev, &st));
+  if (st < 0) return (int)st;
+  if (k_eff) *k_eff = (st == 0) ? k : st - 1;
+  if (st > 0) return (int)st;
+
+  // (S7) R^T = A(I, :)^T (n x k), orthonormal bases by Cholesky-QR2
+  RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, ws_ptr<double>(ctx, o_W), k));
+  RPID_CHECK(transpose_f64(ctx, k, n, ws_ptr<double>(ctx, o_W), k, Rt, n));
+  double* R1c = F;
+  double* R1r = F + kk;
+  double* R2c = F + 2 * kk;
+  double* R2r = F + 3 * kk;
+  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C64, Rt, R1c, R1r, status_dev, 0.0, o_tmp));
+  int64_t st2[2] = {0, 0};
+  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 2 * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+  RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  st2[0] = ctx->host_status[0];
+  st2[1] = ctx->host_status[1];
+  if (st2[0] != 0 || st2[1] != 0) return RPID_ERR_BREAKDOWN;
+  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C64, Rt, R2c, R2r, status_dev, 0.0, o_tmp));
+
+  // W = Q_C^T A (k x n), in the arithmetic of A's storage
+  double* W = ws_ptr<double>(ctx, o_W);
+  if (a_t == RPID_F64) {
+    RPID_CHECK(sketch_f64(ctx, C64, m, (const double*)A, lda, m, n, k, W, k, o_tmp));
+  } else if (a_t == RPID_F32) {
+    float* Pt = ws_ptr<float>(ctx, o_Pt);
+    float* W32 = ws_ptr<float>(ctx, o_W2);
+    RPID_CHECK(convert_matrix<double, float>(ctx, m, k, C64, m, Pt, m));
+    RPID_CHECK(sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, k, W32, k, o_tmp));
+    RPID_CHECK(convert_matrix<float, double>(ctx, k, n, W32, k, W, k));
+  } else {
+    uint16_t* Pt = ws_ptr<uint16_t>(ctx, o_Pt);
+    float* W2 = ws_ptr<float>(ctx, o_W2);
+    RPID_CHECK(split_bf16(ctx, m, k, C64, m, 2, Pt, m));
+    RPID_CHECK(sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, 2 * k, W2, 2 * k, o_tmp));
+    hipLaunchKernelGGL(sum_halves_kernel, dim3(4096), dim3(256), 0, ctx->stream, k, n, W2, W);
+    RPID_HIP_CHECK(hipGetLastError());
+  }
+  // M = W Q_R (k x k)
+  double* M = ws_ptr<double>(ctx, o_M);
+  RPID_CHECK(dgemm(ctx, false, false, k, k, n, 1.0, W, k, Rt, n, 0.0, M, k, o_tmp));
+  // U = R_C^{-1} M R_R^{-T}, R_C = R2c R1c, R_R = R2r R1r
+  RPID_CHECK(tri_solve<double>(ctx, k, k, R2c, k, false, false, false, M, 1, k, M, 1, k));
+  RPID_CHECK(tri_solve<double>(ctx, k, k, R1c, k, false, false, false, M, 1, k, M, 1, k));
+  // rows of Y = M: U(r, :)^T solves R_R u = y_r
+  RPID_CHECK(tri_solve<double>(ctx, k, k, R2r, k, false, false, false, M, k, 1, M, k, 1));
+  RPID_CHECK(tri_solve<double>(ctx, k, k, R1r, k, false, false, false, M, k, 1, M, k, 1));
+  RPID_CHECK(convert_matrix<double, double>(ctx, k, k, M, k, U, ldu));
+  return RPID_OK;
+}
+
+// ---------------------------------------------------------------------------
+template <typename TA>
+static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, int64_t m,
+                         int64_t n, int64_t lda, int64_t k, const int64_t* J, const double* Z,
+                         int64_t ldz, const int64_t* I, const double* U, int64_t ldu,
+                         double* rel_fro) {
+  const bool bf = a_t == RPID_BF16;
+  constexpr int kParts = 3;  // BF16 terms of an FP64 factor
+  Carve cv;
+  const size_t o_out = cv.take<double>(8);
+  const size_t o_P = cv.take<double>((size_t)m * k);
+  const size_t o_Q = cv.take<double>((size_t)k * n);
+  const size_t o_Pb = bf ? cv.take<uint16_t>((size_t)m * kParts * k) : 0;
+  const size_t o_Qb = bf ? cv.take<uint16_t>((size_t)kParts * k * n) : 0;
+  const size_t o_Qs = bf ? cv.take<uint16_t>((size_t)kParts * k * n) : 0;
+  const size_t o_part = cv.take<double>(residual_partials(m, n, bf) + 16);
+  const size_t o_tmp = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, o_tmp + (size_t)64 * k * k * sizeof(double) + 4096));
+  double* out = ws_ptr<double>(ctx, o_out);
+  double* P = ws_ptr<double>(ctx, o_P);
+  double* Q = ws_ptr<double>(ctx, o_Q);
+  double* part = ws_ptr<double>(ctx, o_part);
+  const double* Qp;
+  int64_t ldq;
+  if (which == RPID_RESIDUAL_ID) {
+    // P = C = A(:, J), Q = Z
+    if (!bf) RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, P, m));
+    Qp = Z;
+    ldq = ldz;
+  } else {
+    // P = C U, Q = R = A(I, :)
+    RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, Q, m));  // C into Q scratch
+    RPID_CHECK(dgemm(ctx, false, false, m, k, k, 1.0, Q, m, U, ldu, 0.0, P, m, o_tmp));
+    RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, Q, k));
+    Qp = Q;
+    ldq = k;
+  }
+  if (!bf) {
+    RPID_CHECK(residual_f64<TA>(ctx, m, n, k, A, lda, P, m, Qp, ldq, part, out));
+  } else {
+    // BF16 storage: the BF16 factor (C or R) is exact; the FP64 factor (Z or
+    // C U) is split into kParts BF16 terms along r.
+    uint16_t* Pb = ws_ptr<uint16_t>(ctx, o_Pb);
+    uint16_t* Qb = ws_ptr<uint16_t>(ctx, o_Qb);
+    if (which == RPID_RESIDUAL_ID) {
+      for (int p = 0; p < kParts; ++p)
+        RPID_CHECK(gather_columns<TA, uint16_t>(ctx, m, k, A, lda, n, J, Pb + (int64_t)p * k * m,
+                                                m));
+      // Q' (kParts k x n): rows [p k, (p+1) k) hold term p of Z
+      uint16_t* Qs = ws_ptr<uint16_t>(ctx, o_Qs);
+      RPID_CHECK(split_bf16(ctx, k, n, Qp, ldq, kParts, Qs, k));  // k x (kParts n)
+      // restack: term p block (k x n at column offset p n) -> rows p k of Qb
+      for (int p = 0; p < kParts; ++p)
+        RPID_CHECK(convert_matrix<uint16_t, uint16_t>(ctx, k, n, Qs + (int64_t)p * n * k, k,
+                                                      Qb + (int64_t)p * k, kParts * k));
+    } else {
+      RPID_CHECK(split_bf16(ctx, m, k, P, m, kParts, Pb, m));  // m x (kParts k)
+      for (int p = 0; p < kParts; ++p)
+        RPID_CHECK(gather_rows<TA, uint16_t>(ctx, k, n, A, lda, m, I, Qb + (int64_t)p * k,
+                                             kParts * k));
+    }
+    RPID_CHECK(residual_bf16(ctx, m, n, kParts * k, (const uint16_t*)A, lda, Pb, m, Qb,
+                             kParts * k, part, out));
+  }
+  double h[2];
+  RPID_CHECK(read_doubles(ctx, out, h, 2));
+  *rel_fro = (h[1] > 0.0) ? sqrt(h[0] / h[1]) : 0.0;
+  return RPID_OK;
+}
+
+}  // namespace rpid
+
+using namespace rpid;
+
+extern "C" {
+
+int rpid_version(void) { return 1; }
+
+const char* rpid_status_string(int s) {
+  if (s == RPID_OK) return "ok";
+  if (s > 0) return "exactly zero pivot (rank deficiency); status-1 pivots are defined";
+  switch (s) {
+    case RPID_ERR_NONFINITE: return "non-finite entry in a matrix handed to pivoting";
+    case RPID_ERR_HIP: return "HIP runtime call failed";
+    case RPID_ERR_NOMEM: return "workspace allocation failed";
+    case RPID_ERR_UNSUPPORTED: return "dtype combination or size not supported";
+    case RPID_ERR_LAUNCH: return "cooperative launch could not co-schedule the grid";
+    case RPID_ERR_TIMEOUT: return "device-side wait exceeded its spin limit";
+    case RPID_ERR_BREAKDOWN: return "Cholesky breakdown while orthonormalising C or R^T";
+    default: return "invalid argument (status = -position)";
+  }
+}
+
+int rpid_create(rpid_ctx* out, int device, void* hip_stream) {
+  if (!out) return -1;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return RPID_ERR_HIP;
+  if (device < 0 || device >= ndev) return -2;
+  RPID_HIP_CHECK(hipSetDevice(device));
+  rpid_ctx c = new (std::nothrow) rpid_ctx_s();
+  if (!c) return RPID_ERR_NOMEM;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return RPID_ERR_HIP;
+  }
+  c->num_cu = prop.multiProcessorCount;
+  if (hipHostMalloc((void**)&c->host_status, 64, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RPID_ERR_HIP;
+  }
+  *out = c;
+  return RPID_OK;
+}
+
+int rpid_destroy(rpid_ctx ctx) {
+  if (!ctx) return -1;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->host_status) hipHostFree(ctx->host_status);
+  delete ctx;
+  return RPID_OK;
+}
+
+int rpid_set_stream(rpid_ctx ctx, void* hip_stream) {
+  if (!ctx) return -1;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return RPID_OK;
+}
+
+// ---------------------------------------------------------------------------
+int rpid_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo, void* X, rpid_dtype x_t,
+                int64_t ldx) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (!Omega) return -7;
+  if (l < 1 || l > 1024) return -9;
+  if (ldo < l) return -10;
+  if (!X) return -11;
+  if (ldx < l) return -13;
+  const bool f64 = a_t == RPID_F64 && o_t == RPID_F64 && x_t == RPID_F64;
+  const bool f32 = a_t == RPID_F32 && o_t == RPID_F32 && x_t == RPID_F32;
+  const bool bf = a_t == RPID_BF16 && o_t == RPID_BF16 && x_t == RPID_F32;
+  if (!(f64 || f32 || bf)) return RPID_ERR_UNSUPPORTED;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  const size_t es = esize(a_t);
+  Carve cv;
+  const size_t o_pt = cv.take<char>((size_t)m * l * es + 64);
+  const size_t ws_sk = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, ws_sk + sketch_workspace_bytes(ctx, m, n, l, f64 ? 8 : 4)));
+  // Pt = Omega^T, m x l column-major (rows of Omega contiguous)
+  if (f64) {
+    double* Pt = ws_ptr<double>(ctx, o_pt);
+    RPID_CHECK(transpose_copy<double>(ctx, l, m, (const double*)Omega, ldo, Pt, m));
+    return sketch_f64(ctx, Pt, m, (const double*)A, lda, m, n, l, (double*)X, ldx, ws_sk);
+  }
+  if (f32) {
+    float* Pt = ws_ptr<float>(ctx, o_pt);
+    RPID_CHECK(transpose_copy<float>(ctx, l, m, (const float*)Omega, ldo, Pt, m));
+    return sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
+  }
+  uint16_t* Pt = ws_ptr<uint16_t>(ctx, o_pt);
+  RPID_CHECK(transpose_copy<uint16_t>(ctx, l, m, (const uint16_t*)Omega, ldo, Pt, m));
+  return sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
+}
+
+int rpid_sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda,
+                    const float* Omega, int64_t l, int64_t ldo, float* X, int64_t ldx) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (lda < m) return -5;
+  if (!Omega) return -6;
+  if (l < 1 || l > 1024) return -7;
+  if (ldo < l) return -8;
+  if (!X) return -9;
+  if (ldx < l) return -10;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  RPID_CHECK(ensure_workspace(ctx, sketch_fp8_workspace(m, n, l)));
+  return sketch_fp8(ctx, A, m, n, lda, Omega, l, ldo, X, ldx, 0);
+}
+
+// ---------------------------------------------------------------------------
+int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                        int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
+                        int64_t ldu, void* diagU, int64_t* k_eff) {
+  if (!ctx) return -1;
+  if (!X) return -2;
+  if (!is_lupp_type(x_t)) return -3;
+  if (l < 1) return -4;
+  if (n < 1) return -5;
+  if (ldx < l) return -6;
+  if (k < 1 || k > l || k > n || k > 1024) return -7;
+  if (!J) return -8;
+  if (!Lf) return -9;
+  if (ldl < n) return -10;
+  if (!Uf) return -11;
+  if (ldu < k) return -12;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  const int es = (int)esize(x_t);
+  Carve cv;
+  const size_t o_status = cv.take<int64_t>(8);
+  const size_t o_lupp = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, o_lupp + lupp_workspace_bytes(ctx, n, k, es)));
+  int64_t* status_dev = ws_ptr<int64_t>(ctx, o_status);
+  // Xᵀ panel: P(i, j) = X[j + i * ldx]
+  int s;
+  if (x_t == RPID_F64)
+    s = lupp_panel<double>(ctx, (const double*)X, ldx, 1, n, k, J, (double*)Lf, ldl, (double*)Uf,
+                           ldu, (double*)diagU, o_lupp, status_dev);
+  else
+    s = lupp_panel<float>(ctx, (const float*)X, ldx, 1, n, k, J, (float*)Lf, ldl, (float*)Uf, ldu,
+                          (float*)diagU, o_lupp, status_dev);
+  if (s != RPID_OK) return s;
+  if (!k_eff) return RPID_OK;
+  int64_t st = 0;
+  RPID_CHECK(read_status(ctx, status_dev, &st));
+  if (st < 0) return (int)st;
+  *k_eff = (st == 0) ? k : st - 1;
+  return (int)st;
+}
+
+// ---------------------------------------------------------------------------
+int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                   int64_t ldx, int64_t k, const int64_t* J, const void* Lf, int64_t ldl,
+                   const void* Uf, int64_t ldu, double* Z, int64_t ldz, int refine_steps,
+                   double* eta) {
+  if (!ctx) return -1;
+  if (!X) return -2;
+  if (!is_lupp_type(x_t)) return -3;
+  if (l < 1) return -4;
+  if (n < 1) return -5;
+  if (ldx < l) return -6;
+  if (k < 1 || k > l || k > n || k > 1024) return -7;
+  if (!J) return -8;
+  if (!Lf) return -9;
+  if (ldl < n) return -10;
+  if (!Uf) return -11;
+  if (ldu < k) return -12;
+  if (!Z) return -13;
+  if (ldz < k) return -14;
+  if (refine_steps < 0 || refine_steps > 4) return -15;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_LJ = cv.take<double>((size_t)k * k);
+  const size_t o_U64 = cv.take<double>((size_t)k * k);
+  const size_t o_X1 = cv.take<double>((size_t)k * k);
+  const size_t o_res = refine_steps ? cv.take<double>((size_t)k * n) : 0;
+  const size_t o_G = cv.take<double>((size_t)k * k);
+  const size_t o_lam = cv.take<double>(8);
+  const size_t o_tmp = cv.off;
+  const size_t tmp_bytes = (size_t)64 * k * k * sizeof(double) + 4096;
+  RPID_CHECK(ensure_workspace(ctx, o_tmp + tmp_bytes));
+  double* LJ = ws_ptr<double>(ctx, o_LJ);
+  const bool f64 = x_t == RPID_F64;
+  // L_J = Lf(J, 0:k) in FP64
+  if (f64)
+    RPID_CHECK(gather_rows<double, double>(ctx, k, k, (const double*)Lf, ldl, n, J, LJ, k));
+  else
+    RPID_CHECK(gather_rows<float, double>(ctx, k, k, (const float*)Lf, ldl, n, J, LJ, k));
+  // Z(:, j) solves L_J^T z = Lf(j, :)^T for every column j
+  if (f64)
+    RPID_CHECK(tri_solve<double>(ctx, k, n, LJ, k, true, false, true, (const double*)Lf, ldl, 1,
+                                 Z, 1, ldz));
+  else
+    RPID_CHECK(tri_solve<float>(ctx, k, n, LJ, k, true, false, true, (const float*)Lf, ldl, 1, Z,
+                                1, ldz));
+  RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
+  if (refine_steps > 0) {
+    double* U64 = ws_ptr<double>(ctx, o_U64);
+    double* X1 = ws_ptr<double>(ctx, o_X1);
+    double* res = ws_ptr<double>(ctx, o_res);
+    if (f64) {
+      RPID_CHECK(convert_matrix<double, double>(ctx, k, k, (const double*)Uf, ldu, U64, k));
+      RPID_CHECK(gather_columns<double, double>(ctx, k, k, (const double*)X, ldx, n, J, X1, k));
+    } else {
+      RPID_CHECK(convert_matrix<float, double>(ctx, k, k, (const float*)Uf, ldu, U64, k));
+      RPID_CHECK(gather_columns<float, double>(ctx, k, k, (const float*)X, ldx, n, J, X1, k));
+    }
+    for (int it = 0; it < refine_steps; ++it) {
+      // res = X_k - X_1 Z (FP64, X promoted)
+      if (f64)
+        RPID_CHECK(convert_matrix<double, double>(ctx, k, n, (const double*)X, ldx, res, k));
+      else
+        RPID_CHECK(convert_matrix<float, double>(ctx, k, n, (const float*)X, ldx, res, k));
+      RPID_CHECK(dgemm(ctx, false, false, k, n, k, -1.0, X1, k, Z, ldz, 1.0, res, k, o_tmp));
+      // X_1 d = res with X_1 = (L_J U')^T = U'^T L_J^T: U'^T y = res, then L_J^T d = y
+      RPID_CHECK(tri_solve<double>(ctx, k, n, U64, k, true, true, false, res, 1, k, res, 1, k));
+      RPID_CHECK(tri_solve<double>(ctx, k, n, LJ, k, true, false, true, res, 1, k, res, 1, k));
+      RPID_CHECK(axpy_matrix(ctx, k, n, 1.0, res, k, Z, ldz));
+      RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
+    }
+  }
+  if (eta) {
+    // eta^2 = 1 + ||Z_rest||_2^2 = lambda_max(Z Z^T) since Z(:, J) = I
+    double* G = ws_ptr<double>(ctx, o_G);
+    double* lam = ws_ptr<double>(ctx, o_lam);
+    RPID_CHECK(dgemm(ctx, false, true, k, k, n, 1.0, Z, ldz, Z, ldz, 0.0, G, k, o_tmp));
+    RPID_CHECK(power_iteration(ctx, k, G, k, 2000, 1e-12, lam));
+    double h = 0.0;
+    RPID_CHECK(read_doubles(ctx, lam, &h, 1));
+    *eta = sqrt(h > 1.0 ? h : 1.0);
+  }
+  return RPID_OK;
+}
+
+int rpid_cur(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+             int64_t k, const int64_t* J, int64_t* I, double* U, int64_t ldu, int64_t* k_eff) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (!(a_t == RPID_F64 || a_t == RPID_F32 || a_t == RPID_BF16)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (k < 1 || k > m || k > n || k > 1024) return -7;
+  if (!J) return -8;
+  if (!I) return -9;
+  if (!U) return -10;
+  if (ldu < k) return -11;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  switch (a_t) {
+    case RPID_F64: return cur_impl<double>(ctx, (const double*)A, a_t, m, n, lda, k, J, I, U, ldu, k_eff);
+    case RPID_F32: return cur_impl<float>(ctx, (const float*)A, a_t, m, n, lda, k, J, I, U, ldu, k_eff);
+    default: return cur_impl<uint16_t>(ctx, (const uint16_t*)A, a_t, m, n, lda, k, J, I, U, ldu, k_eff);
+  }
+}
+
+int rpid_residual(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                  int64_t lda, int64_t k, const int64_t* J, const double* Z, int64_t ldz,
+                  const int64_t* I, const double* U, int64_t ldu, double* rel_fro) {
+  if (!ctx) return -1;
+  if (which != RPID_RESIDUAL_ID && which != RPID_RESIDUAL_CUR) return -2;
+  if (!A) return -3;
+  if (!(a_t == RPID_F64 || a_t == RPID_F32 || a_t == RPID_BF16)) return -4;
+  if (m < 1) return -5;
+  if (n < 1) return -6;
+  if (lda < m) return -7;
+  if (k < 1 || k > m || k > n || k > 1024) return -8;
+  if (!J) return -9;
+  if (which == RPID_RESIDUAL_ID && !Z) return -10;
+  if (which == RPID_RESIDUAL_ID && ldz < k) return -11;
+  if (which == RPID_RESIDUAL_CUR && !I) return -12;
+  if (which == RPID_RESIDUAL_CUR && !U) return -13;
+  if (which == RPID_RESIDUAL_CUR && ldu < k) return -14;
+  if (!rel_fro) return -15;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  switch (a_t) {
+    case RPID_F64:
+      return residual_impl<double>(ctx, which, (const double*)A, a_t, m, n, lda, k, J, Z, ldz, I,
+                                   U, ldu, rel_fro);
+    case RPID_F32:
+      return residual_impl<float>(ctx, which, (const float*)A, a_t, m, n, lda, k, J, Z, ldz, I, U,
+                                  ldu, rel_fro);
+    default:
+      return residual_impl<uint16_t>(ctx, which, (const uint16_t*)A, a_t, m, n, lda, k, J, Z, ldz,
+                                     I, U, ldu, rel_fro);
+  }
+}
+
+// ---------------------------------------------------------------------------
+int rpid_mlp_features(rpid_ctx ctx, const void* diagU, rpid_dtype x_t, int64_t L, int64_t k_eff,
+                      float* feats) {
+  if (!ctx) return -1;
+  if (!diagU) return -2;
+  if (!is_lupp_type(x_t)) return -3;
+  if (L < 1 || L > 4096) return -4;
+  if (k_eff < 0 || k_eff > L) return -5;
+  if (!feats) return -6;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  return mlp_features(ctx, diagU, x_t == RPID_F64, L, k_eff, feats);
+}
+
+int rpid_mlp_forward(rpid_ctx ctx, const float* W, const float* feats, int64_t B, float* yhat,
+                     float* act) {
+  if (!ctx) return -1;
+  if (!W) return -2;
+  if (!feats) return -3;
+  if (B < 1) return -4;
+  if (!yhat) return -5;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  return mlp_forward(ctx, W, feats, B, yhat, act);
+}
+
+int rpid_mlp_backward(rpid_ctx ctx, const float* W, const float* feats, const float* act,
+                      const float* dy, int64_t B, float* dW) {
+  if (!ctx) return -1;
+  if (!W) return -2;
+  if (!feats) return -3;
+  if (!act) return -4;
+  if (!dy) return -5;
+  if (B < 1) return -6;
+  if (!dW) return -7;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  RPID_CHECK(ensure_workspace(ctx, mlp_backward_workspace(B)));
+  return mlp_backward(ctx, W, feats, act, dy, B, dW, 0);
+}
+
+int rpid_mlp_adam(rpid_ctx ctx, float* W, const float* dW, float* m1, float* m2, float lr,
+                  int64_t t) {
+  if (!ctx) return -1;
+  if (!W) return -2;
+  if (!dW) return -3;
+  if (!m1) return -4;
+  if (!m2) return -5;
+  if (!(lr > 0.0f)) return -6;
+  if (t < 1) return -7;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  return mlp_adam(ctx, W, dW, m1, m2, lr, t);
+}
+
+}  // extern "C"

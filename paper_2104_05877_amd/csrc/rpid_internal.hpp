@@ -1,0 +1,168 @@
+// Internal declarations shared by the HIP translation units of librpid.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/rpid.h"
+
+struct rpid_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  // Growable device workspace, carved into regions per call.
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // Pinned host word for status read-back.
+  int64_t* host_status = nullptr;
+};
+
+namespace rpid {
+
+// ---------------------------------------------------------------------------
+// Error handling
+// ---------------------------------------------------------------------------
+#define RPID_HIP_CHECK(...)                    \
+  do {                                         \
+    hipError_t _e = (__VA_ARGS__);             \
+    if (_e != hipSuccess) return RPID_ERR_HIP; \
+  } while (0)
+
+#define RPID_CHECK(...)             \
+  do {                              \
+    int _s = (__VA_ARGS__);         \
+    if (_s != RPID_OK) return _s;   \
+  } while (0)
+
+// Workspace carving: aligned bump allocator over the context's buffer.
+struct Carve {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    size_t at = off;
+    off += count * sizeof(T);
+    return at;
+  }
+};
+// Grow the workspace to at least `bytes` (synchronises the stream before
+// freeing the old buffer).  Called once at the top of an entry point, before
+// any kernel of the call is enqueued; helpers only check their bound.
+int ensure_workspace(rpid_ctx ctx, size_t bytes);
+inline int ws_check(rpid_ctx ctx, size_t end) {
+  return end <= ctx->ws_bytes ? RPID_OK : RPID_ERR_NOMEM;
+}
+template <typename T>
+inline T* ws_ptr(rpid_ctx ctx, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ctx->ws) + off);
+}
+
+// ---------------------------------------------------------------------------
+// Element conversion helpers (device)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) {
+  return __uint_as_float(uint32_t(b) << 16);
+}
+// Round-to-nearest-even float -> bf16 bits (finite inputs).
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return uint16_t(u >> 16);
+}
+template <typename T>
+__device__ __forceinline__ double load_as_double(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ double load_as_double<double>(const double* p, int64_t i) {
+  return p[i];
+}
+template <>
+__device__ __forceinline__ double load_as_double<float>(const float* p, int64_t i) {
+  return (double)p[i];
+}
+template <>
+__device__ __forceinline__ double load_as_double<uint16_t>(const uint16_t* p, int64_t i) {
+  return (double)bf16_bits_to_float(p[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers implemented in the .hip translation units
+// ---------------------------------------------------------------------------
+// Fill `count` 64-bit words with `value` (graph-capture friendly, no memset).
+int launch_fill_u64(rpid_ctx ctx, uint64_t* p, size_t count, uint64_t value);
+
+// LUPP on an n x k panel P(i, j) = base[i * rs + j * cs] (k steps), see lupp.hip.
+template <typename T>
+int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, int64_t k,
+               int64_t* J, T* Lf, int64_t ldl, T* Uf, int64_t ldu, T* diag, size_t ws_off,
+               int64_t* status_dev);
+// Workspace bytes lupp_panel needs for an n x k panel.
+size_t lupp_workspace_bytes(rpid_ctx ctx, int64_t n, int64_t k, int elem_bytes);
+
+// X = P^T A for a "row-contiguous" left operand: P is m x l column-major (ldp),
+// i.e. P^T is l x m with rows contiguous; A m x n (lda); X l x n (ldx).
+int sketch_f64(rpid_ctx ctx, const double* Pt, int64_t ldp, const double* A, int64_t lda,
+               int64_t m, int64_t n, int64_t l, double* X, int64_t ldx, size_t ws_off);
+int sketch_f32(rpid_ctx ctx, const float* Pt, int64_t ldp, const float* A, int64_t lda,
+               int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
+int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
+                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
+size_t sketch_workspace_bytes(rpid_ctx ctx, int64_t m, int64_t n, int64_t l, int elem_acc);
+
+// General FP64 GEMM: C = alpha op(A) op(B) + beta C, column-major.
+int dgemm(rpid_ctx ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t K, double alpha,
+          const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+          int64_t ldc, size_t ws_off);
+
+// Triangular solve with many right-hand sides (FP64): for every r < nrhs,
+// solve op(T) x_r = b_r, op(T) = T or T^T of the k x k matrix T (ldt), with
+// op(T) lower (forward) or upper (backward) triangular and optionally a unit
+// diagonal.  b_r(c) = B[r * bcs + c * brs] (type TB), x_r(c) = X[r * xcs + c * xrs].
+// X may alias B only when the two layouts are identical.
+template <typename TB>
+int tri_solve(rpid_ctx ctx, int64_t k, int64_t nrhs, const double* T, int64_t ldt, bool trans,
+              bool lower_op, bool unit, const TB* B, int64_t brs, int64_t bcs, double* X,
+              int64_t xrs, int64_t xcs);
+
+// Cholesky G = R^T R of `batch` SPD k x k matrices (in place, upper R; the
+// strict lower part is zeroed), one workgroup per matrix.  status[b] = 0 or
+// j+1 for a non-positive / non-finite pivot at column j.
+int cholesky_batched(rpid_ctx ctx, int batch, int64_t k, double* G, int64_t ldg,
+                     int64_t stride, int64_t* status_dev);
+
+// Small element-wise helpers (utils.hip)
+template <typename TS, typename TD>
+int convert_matrix(rpid_ctx ctx, int64_t rows, int64_t cols, const TS* S, int64_t lds, TD* D,
+                   int64_t ldd);
+// C(:, t) = A(:, J[t]) / R(t, :) = A(I[t], :); indices outside the matrix
+// read as zeros (never fault).
+template <typename TS, typename TD>
+int gather_columns(rpid_ctx ctx, int64_t m, int64_t k, const TS* A, int64_t lda, int64_t ncols,
+                   const int64_t* J, TD* C, int64_t ldc);
+template <typename TS, typename TD>
+int gather_rows(rpid_ctx ctx, int64_t k, int64_t n, const TS* A, int64_t lda, int64_t nrows,
+                const int64_t* I, TD* R, int64_t ldr);
+// D += alpha S (FP64, rows x cols)
+int axpy_matrix(rpid_ctx ctx, int64_t rows, int64_t cols, double alpha, const double* S,
+                int64_t lds, double* D, int64_t ldd);
+// Largest eigenvalue of a symmetric positive semi-definite k x k FP64 matrix
+// by power iteration (single workgroup); result written to *lam (device).
+int power_iteration(rpid_ctx ctx, int64_t k, const double* G, int64_t ldg, int max_iter,
+                    double rtol, double* lam);
+// Y (cols x rows) = X^T for an FP64 rows x cols matrix.
+int transpose_f64(rpid_ctx ctx, int64_t rows, int64_t cols, const double* X, int64_t ldx,
+                  double* Y, int64_t ldy);
+// D = S + diag(shift) on a k x k matrix; `shift_from` (device, nullable)
+// gives shift = scale * S-trace-free value computed on device: shift =
+// c * sum_i S(i, i) (trace of a Gram matrix = ||C||_F^2).
+int add_trace_shift(rpid_ctx ctx, int64_t k, double* G, int64_t ldg, double c);
+// Set the columns J[t] of Z (k x n) to e_t.
+int set_identity_columns(rpid_ctx ctx, int64_t k, const int64_t* J, double* Z, int64_t ldz);
+// Split an FP64 matrix into `parts` BF16 terms: S = sum_p D_p (greedy RNE
+// residuals); D is rows x (parts * cols) with part p in columns [p cols, (p+1) cols).
+int split_bf16(rpid_ctx ctx, int64_t rows, int64_t cols, const double* S, int64_t lds, int parts,
+               uint16_t* D, int64_t ldd);
+
+}  // namespace rpid

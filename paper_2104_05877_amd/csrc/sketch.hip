@@ -1,0 +1,347 @@
+// Row sketch X = Omega A (Alg. 2, step 2) on the MFMA units of gfx950.
+//
+// Operands: Pt (= Omega^T) is m x l column-major, so every row of Omega is
+// contiguous along m; A is m x n column-major.  X(r, j) = sum_i Pt(i, r) A(i, j).
+//
+// Tiling (one workgroup = 4 waves):
+//  * a workgroup produces all rows of one l-chunk (up to 16*RT rows) for a
+//    strip of 4*CT*16 columns, over one K-range (split-K);
+//  * A is the streamed operand: each lane loads VEC consecutive elements of
+//    one column (16 or 32 bytes) straight into the MFMA B-operand register;
+//    the MFMA k-slots are permuted so that these VEC values are the lane's
+//    k-values of VEC consecutive MFMAs (the reduction order does not change
+//    the result beyond rounding);
+//  * Omega chunks (16*RT rows x BK) are staged in LDS, double buffered, and
+//    shared by the 4 waves;
+//  * split-K partial sums go to a workspace and a second kernel adds them in
+//    a fixed order (deterministic).
+// The K-range index is the fastest-varying part of the workgroup id, so the
+// workgroups that share an Omega slice land on the same XCD (round-robin
+// dispatch) and keep that slice in the XCD's L2.
+#include "rpid_internal.hpp"
+
+namespace rpid {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// Per-dtype traits: element storage, vector width per lane, accumulator.
+template <typename TE>
+struct MT;
+template <>
+struct MT<double> {
+  using Acc = double;
+  using AccV = v4d;
+  static constexpr int VEC = 4;     // elements per lane load (4 MFMA k-steps of 1)
+  static constexpr int KMFMA = 1;   // k-values per lane per MFMA
+  static constexpr int BK = 16;     // K per LDS stage (LDS: 272 x 20 x 8 B x 2)
+  static constexpr int CT = 2;      // column tiles per wave
+  // accumulator register i of lane-group q holds row q + 4 i of the tile
+  static __device__ __forceinline__ int out_row(int q, int i) { return q + 4 * i; }
+};
+template <>
+struct MT<float> {
+  using Acc = float;
+  using AccV = v4f;
+  static constexpr int VEC = 4;
+  static constexpr int KMFMA = 1;
+  static constexpr int BK = 32;
+  static constexpr int CT = 3;
+  // accumulator register i of lane-group q holds row 4 q + i of the tile
+  static __device__ __forceinline__ int out_row(int q, int i) { return 4 * q + i; }
+};
+template <>
+struct MT<uint16_t> {  // bf16 storage
+  using Acc = float;
+  using AccV = v4f;
+  static constexpr int VEC = 8;
+  static constexpr int KMFMA = 8;
+  static constexpr int BK = 64;
+  static constexpr int CT = 3;
+  static __device__ __forceinline__ int out_row(int q, int i) { return 4 * q + i; }
+};
+
+template <typename TE>
+struct Frag {
+  TE v[MT<TE>::VEC];
+};
+
+template <typename TE>
+__device__ __forceinline__ typename MT<TE>::AccV mfma_step(const Frag<TE>& a, const Frag<TE>& b,
+                                                           int s, typename MT<TE>::AccV c);
+template <>
+__device__ __forceinline__ v4d mfma_step<double>(const Frag<double>& a, const Frag<double>& b,
+                                                 int s, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[s], b.v[s], c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ v4f mfma_step<float>(const Frag<float>& a, const Frag<float>& b, int s,
+                                                v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ v4f mfma_step<uint16_t>(const Frag<uint16_t>& a,
+                                                   const Frag<uint16_t>& b, int s, v4f c) {
+  (void)s;
+  v8bf av, bv;
+  __builtin_memcpy(&av, a.v, 16);
+  __builtin_memcpy(&bv, b.v, 16);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+
+template <typename TE>
+__device__ __forceinline__ void load_frag(Frag<TE>& f, const TE* p) {
+  static_assert(sizeof(Frag<TE>) % 16 == 0, "fragment must be whole 16-byte vectors");
+  const uint4* src = reinterpret_cast<const uint4*>(p);
+  uint4* dst = reinterpret_cast<uint4*>(f.v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(Frag<TE>) / 16); ++i) dst[i] = src[i];
+}
+
+template <typename TE>
+__device__ __forceinline__ void load_frag_guarded(Frag<TE>& f, const TE* col, int64_t k,
+                                                  int64_t m) {
+#pragma unroll
+  for (int i = 0; i < MT<TE>::VEC; ++i) f.v[i] = (k + i < m) ? col[k + i] : TE(0);
+}
+
+template <typename TE>
+struct SketchArgs {
+  const TE* Pt;
+  int64_t ldp;
+  const TE* A;
+  int64_t lda;
+  int64_t m, n;
+  int l;
+  int split;       // number of K-ranges
+  int64_t kchunk;  // K per range (multiple of BK)
+  int ltiles;      // row tiles (of 16) per l-chunk
+  typename MT<TE>::Acc* out;  // partials [split][lchunks*16*ltiles? no: n x ldo] or X
+  int64_t ldo;                // leading dimension of out (rows)
+  int64_t out_split_stride;   // elements between split slices (0 if split == 1)
+};
+
+template <typename TE, int RT, bool ALIGNED>
+__global__ __launch_bounds__(256) void sketch_kernel(SketchArgs<TE> a) {
+  using M = MT<TE>;
+  using AccV = typename M::AccV;
+  constexpr int VEC = M::VEC;
+  constexpr int BK = M::BK;
+  constexpr int CT = M::CT;
+  constexpr int SUB = BK / (4 * VEC);        // lane-loads per column per stage
+  constexpr int LROW = BK + 16 / (int)sizeof(TE) * 2;  // padded LDS row (elements)
+  constexpr int ROWS = 16 * RT;
+
+  __shared__ __attribute__((aligned(16))) TE lds[2][ROWS * LROW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int q = lane >> 4;   // k-slot group
+  const int c16 = lane & 15;
+
+  // workgroup -> (split, column strip, l-chunk); split fastest (XCD-aware)
+  const int bid = blockIdx.x;
+  const int split_id = bid % a.split;
+  const int rest = bid / a.split;
+  const int64_t ncolstrips = (a.n + 4 * CT * 16 - 1) / (4 * CT * 16);
+  const int strip = (int)(rest % ncolstrips);
+  const int lchunk = (int)(rest / ncolstrips);
+
+  const int row_base = lchunk * ROWS;
+  const int rt_act = min(RT, (a.l - row_base + 15) / 16);
+  const int64_t kbeg = (int64_t)split_id * a.kchunk;
+  const int64_t kend = min(a.m, kbeg + a.kchunk);
+  const int64_t col_base = (int64_t)strip * (4 * CT * 16) + wid * (CT * 16);
+
+  AccV acc[RT][CT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[r][c] = AccV{};
+
+  // Stage an Omega chunk [row_base, row_base + ROWS) x [k0, k0 + BK) into LDS.
+  auto stage = [&](int buf, int64_t k0) {
+    constexpr int EPV = 16 / (int)sizeof(TE);  // elements per 16-byte vector
+    constexpr int VPR = BK / EPV;               // vectors per row
+    for (int v = tid; v < ROWS * VPR; v += 256) {
+      const int r = v / VPR;
+      const int kk = (v % VPR) * EPV;
+      const int grow = row_base + r;
+      TE* dst = &lds[buf][r * LROW + kk];
+      if (grow < a.l && ALIGNED && k0 + kk + EPV <= kend) {
+        *reinterpret_cast<uint4*>(dst) =
+            *reinterpret_cast<const uint4*>(a.Pt + (int64_t)grow * a.ldp + k0 + kk);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPV; ++e) {
+          const int64_t kg = k0 + kk + e;
+          dst[e] = (grow < a.l && kg < kend) ? a.Pt[(int64_t)grow * a.ldp + kg] : TE(0);
+        }
+      }
+    }
+  };
+
+  if (kbeg < kend) stage(0, kbeg);
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    if (k0 + BK < kend) stage(buf ^ 1, k0 + BK);
+    const bool full = ALIGNED && (k0 + BK <= kend);
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub) {
+      // B-operand fragments (columns of A) for this sub-step
+      Frag<TE> bf[CT];
+      const int64_t kk = k0 + sub * 4 * VEC + q * VEC;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int64_t col = col_base + c * 16 + c16;
+        if (col < a.n) {
+          const TE* cp = a.A + col * a.lda;
+          if (full)
+            load_frag(bf[c], cp + kk);
+          else
+            load_frag_guarded(bf[c], cp, kk, kend);
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) bf[c].v[i] = TE(0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        if (r < rt_act) {
+          Frag<TE> af;
+          load_frag(af, &lds[buf][(r * 16 + c16) * LROW + sub * 4 * VEC + q * VEC]);
+#pragma unroll
+          for (int s = 0; s < VEC / M::KMFMA; ++s)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[r][c] = mfma_step<TE>(af, bf[c], s, acc[r][c]);
+        }
+      }
+    }
+    buf ^= 1;
+  }
+
+  // Write the tile: acc[r][c][i] is row 16r + out_row(q, i), column 16c + c16.
+  typename M::Acc* out = a.out + (int64_t)split_id * a.out_split_stride;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    if (r < rt_act) {
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int64_t col = col_base + c * 16 + c16;
+        if (col < a.n) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = row_base + r * 16 + M::out_row(q, i);
+            if (row < a.l) out[row + col * a.ldo] = acc[r][c][i];
+          }
+        }
+      }
+    }
+  }
+}
+
+// X(r, j) = sum_s part[s](r, j) in a fixed order, converted to the X type.
+template <typename TA, typename TX>
+__global__ void split_reduce_kernel(const TA* part, int split, int64_t stride, int64_t l,
+                                    int64_t n, int64_t ldp, TX* X, int64_t ldx) {
+  const int64_t total = l * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % l, j = e / l;
+    TA s = part[r + j * ldp];
+    for (int t = 1; t < split; ++t) s += part[(int64_t)t * stride + r + j * ldp];
+    X[r + j * ldx] = (TX)s;
+  }
+}
+
+template <typename TE>
+static int sketch_impl(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int64_t lda,
+                       int64_t m, int64_t n, int64_t l, typename MT<TE>::Acc* X, int64_t ldx,
+                       size_t ws_off) {
+  using M = MT<TE>;
+  using Acc = typename M::Acc;
+  constexpr int RT = 17;  // up to 272 rows per l-chunk
+  if (l < 1 || l > 1024 || m < 1 || n < 1) return RPID_ERR_UNSUPPORTED;
+  const int lchunks = (int)((l + 16 * RT - 1) / (16 * RT));
+  const int ltiles = (int)((l + 15) / 16);
+  const int64_t colw = 4 * M::CT * 16;
+  const int64_t strips = (n + colw - 1) / colw;
+  // Split K so that the grid holds about two workgroups per CU.
+  const int64_t base_wgs = strips * lchunks;
+  int64_t split = (2 * (int64_t)ctx->num_cu + base_wgs - 1) / base_wgs;
+  const int64_t kblocks = (m + M::BK - 1) / M::BK;
+  if (split > kblocks) split = kblocks;
+  if (split > 16) split = 16;
+  if (split < 1) split = 1;
+  int64_t kchunk = ((kblocks + split - 1) / split) * M::BK;
+  split = (m + kchunk - 1) / kchunk;
+
+  const bool aligned = ((uintptr_t)A % 16 == 0) && ((uintptr_t)Pt % 16 == 0) &&
+                       (lda * (int64_t)sizeof(TE)) % 16 == 0 &&
+                       (ldp * (int64_t)sizeof(TE)) % 16 == 0;
+
+  SketchArgs<TE> a;
+  a.Pt = Pt;
+  a.ldp = ldp;
+  a.A = A;
+  a.lda = lda;
+  a.m = m;
+  a.n = n;
+  a.l = (int)l;
+  a.split = (int)split;
+  a.kchunk = kchunk;
+  a.ltiles = ltiles;
+  if (split == 1) {
+    a.out = X;
+    a.ldo = ldx;
+    a.out_split_stride = 0;
+  } else {
+    Carve cv;
+    cv.off = ws_off;
+    size_t o_part = cv.take<Acc>((size_t)split * l * n);
+    RPID_CHECK(ws_check(ctx, cv.off));
+    a.out = ws_ptr<Acc>(ctx, o_part);
+    a.ldo = l;
+    a.out_split_stride = l * n;
+  }
+  const int64_t grid = split * strips * lchunks;
+  if (aligned)
+    hipLaunchKernelGGL((sketch_kernel<TE, RT, true>), dim3((unsigned)grid), dim3(256), 0,
+                       ctx->stream, a);
+  else
+    hipLaunchKernelGGL((sketch_kernel<TE, RT, false>), dim3((unsigned)grid), dim3(256), 0,
+                       ctx->stream, a);
+  RPID_HIP_CHECK(hipGetLastError());
+  if (split > 1) {
+    int64_t blocks = (l * n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((split_reduce_kernel<Acc, Acc>), dim3((unsigned)blocks), dim3(256), 0,
+                       ctx->stream, a.out, (int)split, l * n, l, n, l, X, ldx);
+    RPID_HIP_CHECK(hipGetLastError());
+  }
+  return RPID_OK;
+}
+
+size_t sketch_workspace_bytes(rpid_ctx ctx, int64_t m, int64_t n, int64_t l, int acc_bytes) {
+  (void)ctx;
+  (void)m;
+  return (size_t)16 * l * n * acc_bytes + 512;
+}
+
+int sketch_f64(rpid_ctx ctx, const double* Pt, int64_t ldp, const double* A, int64_t lda,
+               int64_t m, int64_t n, int64_t l, double* X, int64_t ldx, size_t ws_off) {
+  return sketch_impl<double>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+}
+int sketch_f32(rpid_ctx ctx, const float* Pt, int64_t ldp, const float* A, int64_t lda,
+               int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+  return sketch_impl<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+}
+int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
+                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+  return sketch_impl<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+}
+
+}  // namespace rpid

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of librpid (include/rpid.h): argument marshalling only.
+
+Every function carries the name of the C entry point it calls.  Matrices are
+torch tensors on the GPU in column-major layout: an m x n matrix is a tensor
+``t`` of shape (m, n) with ``t.stride() == (1, ld)``, ``ld >= m`` (e.g. the
+transpose of a contiguous (n, m) tensor).  Index vectors are int64 tensors.
+All calls enqueue on the stream given to :class:`Context` (by default torch's
+current stream).  There is no fallback: if the HIP library is missing or the
+GPU is absent, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpid.so")
+
+F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
+RESIDUAL_ID, RESIDUAL_CUR = 0, 1
+MLP_IN, MLP_H = 512, 128
+MLP_NPARAM = 128 * 512 + 128 + 128 * 128 + 128 + 128 + 1
+
+ERR = {
+    -100: "NONFINITE",
+    -101: "HIP",
+    -102: "NOMEM",
+    -103: "UNSUPPORTED",
+    -104: "LAUNCH",
+    -105: "TIMEOUT",
+    -106: "BREAKDOWN",
+}
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int64
+_i = ctypes.c_int
+
+_SIGS = {
+    "rpid_create": (_i, [ctypes.POINTER(_P), _i, _P]),
+    "rpid_destroy": (_i, [_P]),
+    "rpid_set_stream": (_i, [_P, _P]),
+    "rpid_status_string": (ctypes.c_char_p, [_i]),
+    "rpid_version": (_i, []),
+    "rpid_sketch": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
+    "rpid_sketch_fp8": (_i, [_P, _P, _I, _I, _I, _P, _I, _I, _P, _I]),
+    "rpid_select_columns": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, ctypes.POINTER(_I)]),
+    "rpid_id_coeffs": (
+        _i,
+        [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, _I, _i, ctypes.POINTER(ctypes.c_double)],
+    ),
+    "rpid_cur": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _P, _I, ctypes.POINTER(_I)]),
+    "rpid_residual": (
+        _i,
+        [_P, _i, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, ctypes.POINTER(ctypes.c_double)],
+    ),
+    "rpid_mlp_features": (_i, [_P, _P, _i, _I, _I, _P]),
+    "rpid_mlp_forward": (_i, [_P, _P, _P, _I, _P, _P]),
+    "rpid_mlp_backward": (_i, [_P, _P, _P, _P, _P, _I, _P]),
+    "rpid_mlp_adam": (_i, [_P, _P, _P, _P, _P, ctypes.c_float, _I]),
+}
+
+
+class RpidError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        name = ERR.get(status, f"argument {-status} invalid" if status < 0 else "zero pivot")
+        super().__init__(f"{fn} failed with status {status} ({name})")
+
+
+def lib():
+    """Load librpid.so (built in-tree by paper_2104_05877_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library not built: {LIB_PATH} is missing "
+                "(run python -m paper_2104_05877_amd.build)"
+            )
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def symbols():
+    """Names of the entry points the binding expects the library to export."""
+    return list(_SIGS)
+
+
+def _check(fn, status, allow_positive=False):
+    if status < 0 or (status > 0 and not allow_positive):
+        raise RpidError(fn, status)
+    return status
+
+
+def dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def colmajor(t: torch.Tensor):
+    """(pointer, rows, cols, ld) of a column-major GPU matrix."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    rows, cols = t.shape
+    if t.stride(0) != 1 and rows > 1:
+        raise ValueError("matrix must be column-major (stride(0) == 1)")
+    ld = t.stride(1) if cols > 1 else max(rows, 1)
+    if ld < rows:
+        raise ValueError("leading dimension smaller than the row count")
+    return t.data_ptr(), rows, cols, ld
+
+
+def empty_colmajor(rows, cols, dtype, device):
+    return torch.empty((cols, rows), dtype=dtype, device=device).T
+
+
+class Context:
+    """An rpid context bound to a device and a HIP stream (torch's current
+    stream by default)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = _P()
+        _check("rpid_create", L.rpid_create(ctypes.byref(h), device, _P(stream.cuda_stream)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().rpid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def rpid_sketch(ctx: Context, A: torch.Tensor, Omega: torch.Tensor, out_dtype=None) -> torch.Tensor:
+    """X = Omega A (Alg. 2, step 2).  BF16 inputs give an FP32 X."""
+    pa, m, n, lda = colmajor(A)
+    po, l, m2, ldo = colmajor(Omega)
+    if m2 != m:
+        raise ValueError("Omega must have m columns")
+    if out_dtype is None:
+        out_dtype = torch.float32 if A.dtype == torch.bfloat16 else A.dtype
+    X = empty_colmajor(l, n, out_dtype, A.device)
+    px, _, _, ldx = colmajor(X)
+    s = lib().rpid_sketch(ctx.handle, pa, dtype_code(A), m, n, lda, po, dtype_code(Omega), l, ldo, px,
+                          dtype_code(X), ldx)
+    _check("rpid_sketch", s)
+    return X
+
+
+def rpid_sketch_fp8(ctx: Context, A: torch.Tensor, Omega: torch.Tensor) -> torch.Tensor:
+    """FP8 (E4M3, power-of-two scaled) sketch of FP32 A; FP32 X."""
+    pa, m, n, lda = colmajor(A)
+    po, l, _, ldo = colmajor(Omega)
+    X = empty_colmajor(l, n, torch.float32, A.device)
+    px, _, _, ldx = colmajor(X)
+    _check("rpid_sketch_fp8", lib().rpid_sketch_fp8(ctx.handle, pa, m, n, lda, po, l, ldo, px, ldx))
+    return X
+
+
+def rpid_select_columns(ctx: Context, X: torch.Tensor, k: int, sync: bool = True):
+    """Column-wise LUPP on the sketch (Alg. 2, step 3).  Returns
+    (J, Lf, Uf, diagU, k_eff, status); k_eff/status are None when sync=False."""
+    px, l, n, ldx = colmajor(X)
+    J = torch.empty(k, dtype=torch.int64, device=X.device)
+    Lf = empty_colmajor(n, k, X.dtype, X.device)
+    Uf = empty_colmajor(k, k, X.dtype, X.device)
+    diag = torch.empty(k, dtype=X.dtype, device=X.device)
+    keff = _I(-1)
+    s = lib().rpid_select_columns(
+        ctx.handle, px, dtype_code(X), l, n, ldx, k, J.data_ptr(), Lf.data_ptr(), Lf.stride(1),
+        Uf.data_ptr(), Uf.stride(1), diag.data_ptr(), ctypes.byref(keff) if sync else None,
+    )
+    _check("rpid_select_columns", s, allow_positive=True)
+    return J, Lf, Uf, diag, (keff.value if sync else None), (s if sync else None)
+
+
+def rpid_id_coeffs(ctx, X, k, J, Lf, Uf, refine_steps=0, want_eta=False):
+    """Z (k x n, FP64) with Z(:, J) = I from the pivoted sketch (Sec. 4), and
+    optionally Theorem 1's eta."""
+    px, l, n, ldx = colmajor(X)
+    Z = empty_colmajor(k, n, torch.float64, X.device)
+    eta = ctypes.c_double(0.0)
+    s = lib().rpid_id_coeffs(
+        ctx.handle, px, dtype_code(X), l, n, ldx, k, J.data_ptr(), Lf.data_ptr(), Lf.stride(1),
+        Uf.data_ptr(), Uf.stride(1), Z.data_ptr(), Z.stride(1), int(refine_steps),
+        ctypes.byref(eta) if want_eta else None,
+    )
+    _check("rpid_id_coeffs", s)
+    return Z, (eta.value if want_eta else None)
+
+
+def rpid_cur(ctx, A, k, J):
+    """Row skeleton I (LUPP on C = A(:, J)) and U = C^+ A R^+ (stable form).
+    Returns (I, U, k_eff, status)."""
+    pa, m, n, lda = colmajor(A)
+    I = torch.empty(k, dtype=torch.int64, device=A.device)
+    U = empty_colmajor(k, k, torch.float64, A.device)
+    keff = _I(-1)
+    s = lib().rpid_cur(ctx.handle, pa, dtype_code(A), m, n, lda, k, J.data_ptr(), I.data_ptr(),
+                       U.data_ptr(), U.stride(1), ctypes.byref(keff))
+    _check("rpid_cur", s, allow_positive=True)
+    return I, U, keff.value, s
+
+
+def rpid_residual(ctx, which, A, k, J, Z=None, I=None, U=None) -> float:
+    """||A - C Z||_F / ||A||_F (which=RESIDUAL_ID) or ||A - C U R||_F / ||A||_F."""
+    pa, m, n, lda = colmajor(A)
+    out = ctypes.c_double(0.0)
+    s = lib().rpid_residual(
+        ctx.handle, int(which), pa, dtype_code(A), m, n, lda, k, J.data_ptr(),
+        Z.data_ptr() if Z is not None else None, Z.stride(1) if Z is not None else k,
+        I.data_ptr() if I is not None else None,
+        U.data_ptr() if U is not None else None, U.stride(1) if U is not None else k,
+        ctypes.byref(out),
+    )
+    _check("rpid_residual", s)
+    return out.value
+
+
+def rpid_mlp_features(ctx, diagU, L, k_eff):
+    f = torch.empty(L, dtype=torch.float32, device=diagU.device)
+    _check("rpid_mlp_features",
+           lib().rpid_mlp_features(ctx.handle, diagU.data_ptr(), dtype_code(diagU), L, k_eff, f.data_ptr()))
+    return f
+
+
+def rpid_mlp_forward(ctx, W, feats, want_act=True):
+    B = feats.shape[0]
+    y = torch.empty(B, dtype=torch.float32, device=feats.device)
+    act = torch.empty((B, 2 * MLP_H), dtype=torch.float32, device=feats.device) if want_act else None
+    _check("rpid_mlp_forward", lib().rpid_mlp_forward(
+        ctx.handle, W.data_ptr(), feats.contiguous().data_ptr(), B, y.data_ptr(),
+        act.data_ptr() if act is not None else None))
+    return y, act
+
+
+def rpid_mlp_backward(ctx, W, feats, act, dy):
+    B = feats.shape[0]
+    dW = torch.empty(MLP_NPARAM, dtype=torch.float32, device=feats.device)
+    _check("rpid_mlp_backward", lib().rpid_mlp_backward(
+        ctx.handle, W.data_ptr(), feats.contiguous().data_ptr(), act.data_ptr(),
+        dy.contiguous().data_ptr(), B, dW.data_ptr()))
+    return dW
+
+
+def rpid_mlp_adam(ctx, W, dW, m1, m2, lr, t):
+    _check("rpid_mlp_adam", lib().rpid_mlp_adam(
+        ctx.handle, W.data_ptr(), dW.data_ptr(), m1.data_ptr(), m2.data_ptr(), float(lr), int(t)))
+
+
+def decompose(ctx, A, Omega, k, refine_steps=None, want_eta=False, want_cur=True):
+    """The whole path: sketch, column LUPP, Z, and (optionally) CUR.  The
+    LUPP runs in FP64 for FP64 storage and in FP32 otherwise."""
+    X = rpid_sketch(ctx, A, Omega)
+    if refine_steps is None:
+        refine_steps = 0 if X.dtype == torch.float64 else 1
+    J, Lf, Uf, diag, keff, st = rpid_select_columns(ctx, X, k)
+    out = dict(X=X, J=J, Lf=Lf, Uf=Uf, diag=diag, k_eff=keff, status=st)
+    if st != 0:
+        return out
+    Z, eta = rpid_id_coeffs(ctx, X, k, J, Lf, Uf, refine_steps=refine_steps, want_eta=want_eta)
+    out.update(Z=Z, eta=eta)
+    if want_cur:
+        I, U, keff_i, st_i = rpid_cur(ctx, A, k, J)
+        out.update(I=I, U=U, status_I=st_i)
+    return out
