@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of randomized LUPP ID + CUR on one MI355X.
+
+Workload (poly8192): A = U diag(s) V^T, 8192 x 8192, s_i = i^-2, U and V
+Haar-orthonormal (seeded, generated on the GPU with torch, rounded to FP32
+storage), Gaussian embedding Omega of l = k + 16 = 272 rows, k = 256.
+
+One step = one pass of the whole path over the resident inputs:
+  sketch X = Omega A  ->  column LUPP on X (J, factors)  ->  Z (+1 FP64
+  refinement in the FP32/BF16 modes)  ->  CUR (LUPP on C -> I, stable U)
+  ->  ID and CUR residuals.
+Modes: bf16 (A and Omega stored BF16; BF16 MFMA sketch, FP32 LUPP, FP64
+Z/U), f32 (FP32 storage and arithmetic for sketch/LUPP), f64 (the FP32
+values of A promoted to FP64; FP64 everywhere).
+
+Prints one JSON line.  `value` is decompositions per second of the main
+mode (default bf16) with the inputs already in HBM.  `roofline` describes
+the kernel that takes the most time per step; `cpu_baseline` times the FP64
+numpy oracle on the host cores on one decomposition of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M = N = 8192
+K = 256
+L = 272
+PEAK_HBM = 8.0e12  # B/s, MI355X HBM3E
+PEAK_MFMA = {"bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}  # dense FLOP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--other-steps", type=int, default=8, help="timed steps of the other two modes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=1)
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_inputs(torch, seed):
+    from paper_2104_05877_amd import inputs
+
+    s = inputs.poly_spectrum(N, 2.0)
+    a64 = inputs.torch_spectral(M, N, s, seed, "cuda")
+    a32 = a64.T.contiguous().float().T  # FP32 storage of the workload
+    del a64
+    om32 = inputs.torch_gaussian(L, M, seed + 7, "cuda").T.contiguous().float().T
+    out = {
+        "f32": (a32, om32),
+        "f64": (a32.T.contiguous().double().T, om32.T.contiguous().double().T),
+        "bf16": (a32.T.contiguous().bfloat16().T, om32.T.contiguous().bfloat16().T),
+    }
+    torch.cuda.synchronize()
+    return out
+
+
+def run_mode(torch, R, ctx, A, Om, steps, warmup):
+    """Time `steps` full steps; per-call HIP-event times on the context stream."""
+    refine = 0 if A.dtype == torch.float64 else 1
+    stream = ctx.stream
+    names = ["sketch", "select_columns", "id_coeffs", "cur", "residual_id", "residual_cur"]
+
+    def step(ev):
+        ev[0].record(stream)
+        X = R.rpid_sketch(ctx, A, Om)
+        ev[1].record(stream)
+        J, Lf, Uf, diag, keff, st = R.rpid_select_columns(ctx, X, K, sync=False)
+        ev[2].record(stream)
+        Z, _ = R.rpid_id_coeffs(ctx, X, K, J, Lf, Uf, refine_steps=refine)
+        ev[3].record(stream)
+        I, U, keff_i, st_i = R.rpid_cur(ctx, A, K, J)
+        ev[4].record(stream)
+        rid = R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, J, Z=Z)
+        ev[5].record(stream)
+        rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, A, K, J, I=I, U=U)
+        ev[6].record(stream)
+        return rid, rcur, st_i, J, I
+
+    def mk():
+        return [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+
+    for _ in range(warmup):
+        step(mk())
+    torch.cuda.synchronize()
+    evs = [mk() for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        out = step(evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = {n: 0.0 for n in names}
+    for ev in evs:
+        for j, n in enumerate(names):
+            per[n] += ev[j].elapsed_time(ev[j + 1]) / steps  # ms
+    rid, rcur, st_i, J, I = out
+    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, per_call_ms=per, rid=rid, rcur=rcur,
+                status_cur=st_i, J=J.cpu().numpy(), I=I.cpu().numpy())
+
+
+def cpu_baseline(torch, A, Om):
+    """The FP64 oracle, untuned, on the host: one decomposition (sketch, LUPP,
+    Z, CUR) plus its ID and CUR residuals on the same stored values."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle.rpid_oracle as O
+
+    a = np.asfortranarray(A.double().cpu().numpy())
+    om = np.asfortranarray(Om.double().cpu().numpy())
+    t0 = time.perf_counter()
+    d = O.decompose(a, om, K)
+    r = O.residuals(a, d["J"], Z=d["Z"], I=d["I"], U=d["U"], only=("id", "cur"))
+    t = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return dict(seconds=t, threads=threads, rid=r["id"], rcur=r["cur"], J=d["J"], I=d["I"])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2104_05877_amd import rpid as R
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    log("generating poly8192 inputs on the GPU")
+    data = make_inputs(torch, args.seed)
+    ctx = R.Context(0)
+    results = {}
+    order = [args.mode] + [m for m in ("bf16", "f32", "f64") if m != args.mode]
+    for mode in order:
+        A, Om = data[mode]
+        steps = args.steps if mode == args.mode else args.other_steps
+        warm = args.warmup if mode == args.mode else 1
+        log(f"mode {mode}: warmup {warm}, steps {steps}")
+        results[mode] = run_mode(torch, R, ctx, A, Om, steps, warm)
+        log(f"mode {mode}: {results[mode]['ms_per_step']:.3f} ms/step  per-call {results[mode]['per_call_ms']}")
+
+    main_r = results[args.mode]
+    per = main_r["per_call_ms"]
+    # Dominant single-kernel call of the main mode: sketch (GEMM + split-K sum)
+    # or the LUPP panel kernel (select_columns: two 8-byte fills + the kernel).
+    es = 8 if args.mode == "f64" else 4
+    lupp_bytes = N * K * es + N * K * es + K * K * es  # read panel, write L, write U
+    a_es = {"f64": 8, "f32": 4, "bf16": 2}[args.mode]
+    sketch_bytes = M * N * a_es + L * M * a_es + L * N * (8 if args.mode == "f64" else 4)
+    sketch_flops = 2.0 * L * M * N
+    t_sk = per["sketch"] * 1e-3
+    t_lu = per["select_columns"] * 1e-3
+    sketch_mfma = sketch_flops / t_sk / PEAK_MFMA[args.mode]
+    if t_lu >= t_sk:
+        ach = lupp_bytes / t_lu
+        roof = {"kernel": "lupp_panel_kernel (column LUPP of X^T, 8192 x 256)", "bound": "hbm",
+                "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": ach / PEAK_HBM, "traffic": None, "avg_ms": per["select_columns"]}
+    else:
+        if args.mode == "bf16":
+            ach = sketch_bytes / t_sk
+            roof = {"kernel": "sketch_kernel + split_reduce (X = Omega A)", "bound": "hbm",
+                    "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM, "traffic": None, "avg_ms": per["sketch"]}
+        else:
+            ach = sketch_flops / t_sk
+            roof = {"kernel": "sketch_kernel + split_reduce (X = Omega A)", "bound": "mfma",
+                    "achieved": ach / 1e12, "peak": PEAK_MFMA[args.mode] / 1e12, "unit": "TFLOP/s",
+                    "frac": ach / PEAK_MFMA[args.mode], "traffic": None, "avg_ms": per["sketch"]}
+
+    line = {
+        "metric": "ID+CUR decomps/sec & sketch-GEMM MFMA util at 8192^2, k=256; BF16 vs FP64",
+        "value": 1e3 / main_r["ms_per_step"],
+        "unit": "decomps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.mode,
+        "data": "synthetic",
+        "config": {"workload": "poly8192", "m": M, "n": N, "k": K, "l": L,
+                   "spectrum": "s_i = i^-2, Haar U and V, FP32 storage", "mode": args.mode,
+                   "step": "sketch + LUPP(X^T) + Z + CUR(LUPP(C), U) + ID/CUR residuals"},
+        "sketch_mfma_util": sketch_mfma,
+        "modes": {m: {"decomps_per_s": 1e3 / r["ms_per_step"], "ms_per_step": r["ms_per_step"],
+                      "per_call_ms": r["per_call_ms"], "residual_id": r["rid"],
+                      "residual_cur": r["rcur"]} for m, r in results.items()},
+        "speedup_bf16_vs_f64": results["f64"]["ms_per_step"] / results["bf16"]["ms_per_step"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle on one decomposition of the same workload")
+        A, Om = data[args.mode]
+        cb = cpu_baseline(torch, A, Om)
+        line["cpu_baseline"] = {"value": 1.0 / cb["seconds"], "unit": "decomps/s",
+                                "cores": cb["threads"], "kind": "oracle",
+                                "sample": "1 decomposition + ID/CUR residuals of poly8192 "
+                                          f"({args.mode} storage values promoted to FP64), "
+                                          f"{cb['seconds']:.2f} s"}
+        line["residual_ratio_vs_oracle"] = {"id": main_r["rid"] / cb["rid"],
+                                            "cur": main_r["rcur"] / cb["rcur"],
+                                            "oracle_id": cb["rid"], "oracle_cur": cb["rcur"],
+                                            "J_equal": bool(np.array_equal(main_r["J"], cb["J"])),
+                                            "I_equal": bool(np.array_equal(main_r["I"], cb["I"]))}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

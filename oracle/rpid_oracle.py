@@ -215,28 +215,32 @@ def rangefinder_error(A, X, k, ord="fro"):
     return float(np.linalg.norm(E, 2) / np.linalg.norm(A, 2))
 
 
-def residuals(A, J, Z=None, I=None, U=None, ord="fro"):
+def residuals(A, J, Z=None, I=None, U=None, ord="fro", only=None):
     """Relative errors; explicit differences (never an expanded form).
 
     id    ||A - A(:,J) Z|| / ||A||          (Z from the sketch, Sec. 4)
     idopt ||A - C C^+ A|| / ||A||           (eq. def_column_id)
     cur   ||A - C U R|| / ||A||             (eq. def_cur)
     rowopt||A - A R^+ R|| / ||A||           (eq. def_row_id)
+    ``only`` (optional) restricts the work to the listed keys.
     """
     A = _f64(A)
     nrm = (lambda e: _fro(e)) if ord == "fro" else (lambda e: float(np.linalg.norm(e, 2)))
     na = nrm(A)
     C = A[:, J]
+    want = (lambda key: only is None or key in only)
     out = {}
-    qc, _ = np.linalg.qr(C)
-    out["idopt"] = nrm(A - qc @ (qc.T @ A)) / na
-    if Z is not None:
+    if want("idopt"):
+        qc, _ = np.linalg.qr(C)
+        out["idopt"] = nrm(A - qc @ (qc.T @ A)) / na
+    if Z is not None and want("id"):
         out["id"] = nrm(A - C @ _f64(Z)) / na
     if I is not None:
         R = A[I, :]
-        qr_, _ = np.linalg.qr(R.T)
-        out["rowopt"] = nrm(A - (A @ qr_) @ qr_.T) / na
-        if U is not None:
+        if want("rowopt"):
+            qr_, _ = np.linalg.qr(R.T)
+            out["rowopt"] = nrm(A - (A @ qr_) @ qr_.T) / na
+        if U is not None and want("cur"):
             out["cur"] = nrm(A - (C @ _f64(U)) @ R) / na
     return out
 

@@ -12,8 +12,12 @@ int residual_f64(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const TA* A, int
                  const double* P, int64_t ldp, const double* Q, int64_t ldq, double* partials,
                  double* out2);
 int residual_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* A, int64_t lda,
-                  const uint16_t* P, int64_t ldp, const uint16_t* Q, int64_t ldq,
+                  const uint16_t* Pt, int64_t ldpt, const uint16_t* Q, int64_t ldq,
                   double* partials, double* out2);
+int pack_cols_t(rpid_ctx ctx, int64_t m, int64_t k, int parts, const uint16_t* A, int64_t lda,
+                int64_t ncols, const int64_t* J, uint16_t* Pt);
+int pack_split_t(rpid_ctx ctx, int64_t m, int64_t k, int parts, const double* P, int64_t ldp,
+                 uint16_t* Pt);
 size_t residual_partials(int64_t m, int64_t n, bool bf16);
 int mlp_forward(rpid_ctx, const float*, const float*, int64_t, float*, float*);
 int mlp_backward(rpid_ctx, const float*, const float*, const float*, const float*, int64_t,
@@ -109,25 +113,22 @@ __global__ void sum_halves_kernel(int64_t k, int64_t n, const float* W2, double*
 }
 
 // ---------------------------------------------------------------------------
-// CUR: shifted/plain Cholesky-QR2 of C (m x k) and R^T (n x k), both FP64,
-// batched.  On return Q_C overwrites C64, Q_R overwrites Rt64, and the
-// factors R_C = R2c R1c, R_R = R2r R1r are left in F (4 k x k matrices:
-// R1c, R1r, R2c, R2r).
+// CUR: one Cholesky-QR pass over C (m x k) and R^T (n x k), both FP64:
+// Gram matrices, batched Cholesky (R upper), triangular inverses, and the
+// orthonormalised factors Qc = C Rc^{-1}, Qr = R^T Rr^{-1} as GEMMs.
+// F holds the two Cholesky factors (stride k*k), Wi their inverses.
 // ---------------------------------------------------------------------------
-static int chol_qr_pass(rpid_ctx ctx, int64_t m, int64_t n, int64_t k, double* C64,
-                        double* Rt64, double* F1c, double* F1r, int64_t* status_dev, double shift,
-                        size_t ws_tmp) {
-  // Gram matrices into F1c / F1r (adjacent: stride k*k)
-  RPID_CHECK(dgemm(ctx, true, false, k, k, m, 1.0, C64, m, C64, m, 0.0, F1c, k, ws_tmp));
-  RPID_CHECK(dgemm(ctx, true, false, k, k, n, 1.0, Rt64, n, Rt64, n, 0.0, F1r, k, ws_tmp));
-  if (shift > 0.0) {
-    RPID_CHECK(add_trace_shift(ctx, k, F1c, k, shift));
-    RPID_CHECK(add_trace_shift(ctx, k, F1r, k, shift));
-  }
-  RPID_CHECK(cholesky_batched(ctx, 2, k, F1c, k, F1r - F1c, status_dev));
-  // Q = X R^{-1}: each row x of X solves R^T q = x
-  RPID_CHECK(tri_solve<double>(ctx, k, m, F1c, k, true, true, false, C64, m, 1, C64, m, 1));
-  RPID_CHECK(tri_solve<double>(ctx, k, n, F1r, k, true, true, false, Rt64, n, 1, Rt64, n, 1));
+static int chol_qr_pass(rpid_ctx ctx, int64_t m, int64_t n, int64_t k, const double* C,
+                        const double* Rt, double* Cq, double* Rq, double* F, double* Wi,
+                        int64_t* status_dev, size_t ws_tmp) {
+  const int64_t kk = k * k;
+  RPID_CHECK(dgemm(ctx, true, false, k, k, m, 1.0, C, m, C, m, 0.0, F, k, ws_tmp));
+  RPID_CHECK(dgemm(ctx, true, false, k, k, n, 1.0, Rt, n, Rt, n, 0.0, F + kk, k, ws_tmp));
+  RPID_CHECK(cholesky_batched(ctx, 2, k, F, k, kk, status_dev));
+  RPID_CHECK(tri_inverse(ctx, k, F, k, false, false, Wi, k));
+  RPID_CHECK(tri_inverse(ctx, k, F + kk, k, false, false, Wi + kk, k));
+  RPID_CHECK(dgemm(ctx, false, false, m, k, k, 1.0, C, m, Wi, k, 0.0, Cq, m, ws_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, n, k, k, 1.0, Rt, n, Wi + kk, k, 0.0, Rq, n, ws_tmp));
   return RPID_OK;
 }
 
@@ -144,7 +145,11 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   const size_t o_Lc = cv.take<double>((size_t)m * k);  // LUPP multipliers (discarded)
   const size_t o_Uc = cv.take<double>((size_t)k * k);
   const size_t o_Rt = cv.take<double>((size_t)n * k);
+  const size_t o_C2 = cv.take<double>((size_t)m * k);
+  const size_t o_Rt2 = cv.take<double>((size_t)n * k);
   const size_t o_F = cv.take<double>((size_t)4 * k * k);
+  const size_t o_Wi = cv.take<double>((size_t)4 * k * k);
+  const size_t o_T = cv.take<double>((size_t)3 * k * k);
   const size_t o_W = cv.take<double>((size_t)k * n);
   const size_t o_W2 = cv.take<float>((size_t)2 * k * n);
   const size_t o_Pt = cv.take<char>((size_t)m * 2 * k * 4);
@@ -182,20 +187,18 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   // (S7) R^T = A(I, :)^T (n x k), orthonormal bases by Cholesky-QR2
   RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, ws_ptr<double>(ctx, o_W), k));
   RPID_CHECK(transpose_f64(ctx, k, n, ws_ptr<double>(ctx, o_W), k, Rt, n));
-  double* R1c = F;
-  double* R1r = F + kk;
-  double* R2c = F + 2 * kk;
-  double* R2r = F + 3 * kk;
-  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C64, Rt, R1c, R1r, status_dev, 0.0, o_tmp));
-  int64_t st2[2] = {0, 0};
+  double* C2 = ws_ptr<double>(ctx, o_C2);
+  double* Rt2 = ws_ptr<double>(ctx, o_Rt2);
+  double* Wi = ws_ptr<double>(ctx, o_Wi);
+  // pass 1: C, R^T -> C2, Rt2 (factors R1c, R1r in F[0..2), inverses in Wi[0..2))
+  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C64, Rt, C2, Rt2, F, Wi, status_dev, o_tmp));
   RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 2 * sizeof(int64_t),
                                 hipMemcpyDeviceToHost, ctx->stream));
   RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-  st2[0] = ctx->host_status[0];
-  st2[1] = ctx->host_status[1];
-  if (st2[0] != 0 || st2[1] != 0) return RPID_ERR_BREAKDOWN;
-  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C64, Rt, R2c, R2r, status_dev, 0.0, o_tmp));
-
+  if (ctx->host_status[0] != 0 || ctx->host_status[1] != 0) return RPID_ERR_BREAKDOWN;
+  // pass 2: C2, Rt2 -> Q_C (into C64), Q_R (into Rt) (factors R2c, R2r, inverses)
+  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C2, Rt2, C64, Rt, F + 2 * kk, Wi + 2 * kk, status_dev,
+                          o_tmp));
   // W = Q_C^T A (k x n), in the arithmetic of A's storage
   double* W = ws_ptr<double>(ctx, o_W);
   if (a_t == RPID_F64) {
@@ -217,13 +220,15 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   // M = W Q_R (k x k)
   double* M = ws_ptr<double>(ctx, o_M);
   RPID_CHECK(dgemm(ctx, false, false, k, k, n, 1.0, W, k, Rt, n, 0.0, M, k, o_tmp));
-  // U = R_C^{-1} M R_R^{-T}, R_C = R2c R1c, R_R = R2r R1r
-  RPID_CHECK(tri_solve<double>(ctx, k, k, R2c, k, false, false, false, M, 1, k, M, 1, k));
-  RPID_CHECK(tri_solve<double>(ctx, k, k, R1c, k, false, false, false, M, 1, k, M, 1, k));
-  // rows of Y = M: U(r, :)^T solves R_R u = y_r
-  RPID_CHECK(tri_solve<double>(ctx, k, k, R2r, k, false, false, false, M, k, 1, M, k, 1));
-  RPID_CHECK(tri_solve<double>(ctx, k, k, R1r, k, false, false, false, M, k, 1, M, k, 1));
-  RPID_CHECK(convert_matrix<double, double>(ctx, k, k, M, k, U, ldu));
+  // U = R_C^{-1} M R_R^{-T} with R_C = R2c R1c, R_R = R2r R1r:
+  // U = (W1c W2c) M (W1r W2r)^T, W = inverses of the Cholesky factors
+  double* Tc = ws_ptr<double>(ctx, o_T);
+  double* Tr = Tc + kk;
+  double* Y = Tc + 2 * kk;
+  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi, k, Wi + 2 * kk, k, 0.0, Tc, k, o_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi + kk, k, Wi + 3 * kk, k, 0.0, Tr, k, o_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Tc, k, M, k, 0.0, Y, k, o_tmp));
+  RPID_CHECK(dgemm(ctx, false, true, k, k, k, 1.0, Y, k, Tr, k, 0.0, U, ldu, o_tmp));
   return RPID_OK;
 }
 
@@ -269,12 +274,11 @@ static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, i
   } else {
     // BF16 storage: the BF16 factor (C or R) is exact; the FP64 factor (Z or
     // C U) is split into kParts BF16 terms along r.
+    // Pb is the k-contiguous (kParts k x m) transpose of P' = [P_0 .. P_{kParts-1}]
     uint16_t* Pb = ws_ptr<uint16_t>(ctx, o_Pb);
     uint16_t* Qb = ws_ptr<uint16_t>(ctx, o_Qb);
     if (which == RPID_RESIDUAL_ID) {
-      for (int p = 0; p < kParts; ++p)
-        RPID_CHECK(gather_columns<TA, uint16_t>(ctx, m, k, A, lda, n, J, Pb + (int64_t)p * k * m,
-                                                m));
+      RPID_CHECK(pack_cols_t(ctx, m, k, kParts, (const uint16_t*)A, lda, n, J, Pb));
       // Q' (kParts k x n): rows [p k, (p+1) k) hold term p of Z
       uint16_t* Qs = ws_ptr<uint16_t>(ctx, o_Qs);
       RPID_CHECK(split_bf16(ctx, k, n, Qp, ldq, kParts, Qs, k));  // k x (kParts n)
@@ -283,12 +287,12 @@ static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, i
         RPID_CHECK(convert_matrix<uint16_t, uint16_t>(ctx, k, n, Qs + (int64_t)p * n * k, k,
                                                       Qb + (int64_t)p * k, kParts * k));
     } else {
-      RPID_CHECK(split_bf16(ctx, m, k, P, m, kParts, Pb, m));  // m x (kParts k)
+      RPID_CHECK(pack_split_t(ctx, m, k, kParts, P, m, Pb));
       for (int p = 0; p < kParts; ++p)
         RPID_CHECK(gather_rows<TA, uint16_t>(ctx, k, n, A, lda, m, I, Qb + (int64_t)p * k,
                                              kParts * k));
     }
-    RPID_CHECK(residual_bf16(ctx, m, n, kParts * k, (const uint16_t*)A, lda, Pb, m, Qb,
+    RPID_CHECK(residual_bf16(ctx, m, n, kParts * k, (const uint16_t*)A, lda, Pb, kParts * k, Qb,
                              kParts * k, part, out));
   }
   double h[2];
@@ -480,8 +484,12 @@ int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64
   RPID_HIP_CHECK(hipSetDevice(ctx->device));
   Carve cv;
   const size_t o_LJ = cv.take<double>((size_t)k * k);
+  const size_t o_Winv = cv.take<double>((size_t)k * k);
+  const size_t o_WU = cv.take<double>((size_t)k * k);
+  const size_t o_P = cv.take<double>((size_t)k * k);
   const size_t o_U64 = cv.take<double>((size_t)k * k);
   const size_t o_X1 = cv.take<double>((size_t)k * k);
+  const size_t o_L64 = x_t == RPID_F64 ? 0 : cv.take<double>((size_t)n * k);
   const size_t o_res = refine_steps ? cv.take<double>((size_t)k * n) : 0;
   const size_t o_G = cv.take<double>((size_t)k * k);
   const size_t o_lam = cv.take<double>(8);
@@ -489,24 +497,31 @@ int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64
   const size_t tmp_bytes = (size_t)64 * k * k * sizeof(double) + 4096;
   RPID_CHECK(ensure_workspace(ctx, o_tmp + tmp_bytes));
   double* LJ = ws_ptr<double>(ctx, o_LJ);
+  double* Winv = ws_ptr<double>(ctx, o_Winv);
   const bool f64 = x_t == RPID_F64;
-  // L_J = Lf(J, 0:k) in FP64
+  // L_J = Lf(J, 0:k) in FP64 and W = L_J^{-1} (unit lower)
   if (f64)
     RPID_CHECK(gather_rows<double, double>(ctx, k, k, (const double*)Lf, ldl, n, J, LJ, k));
   else
     RPID_CHECK(gather_rows<float, double>(ctx, k, k, (const float*)Lf, ldl, n, J, LJ, k));
-  // Z(:, j) solves L_J^T z = Lf(j, :)^T for every column j
-  if (f64)
-    RPID_CHECK(tri_solve<double>(ctx, k, n, LJ, k, true, false, true, (const double*)Lf, ldl, 1,
-                                 Z, 1, ldz));
-  else
-    RPID_CHECK(tri_solve<float>(ctx, k, n, LJ, k, true, false, true, (const float*)Lf, ldl, 1, Z,
-                                1, ldz));
+  RPID_CHECK(tri_inverse(ctx, k, LJ, k, true, true, Winv, k));
+  // Z = W^T Lf^T: column j is L_J^{-T} Lf(j, :)^T, i.e. solves L_J^T z = Lf(j, :)^T
+  const double* L64 = (const double*)Lf;
+  int64_t ldl64 = ldl;
+  if (!f64) {
+    double* Lc = ws_ptr<double>(ctx, o_L64);
+    RPID_CHECK(convert_matrix<float, double>(ctx, n, k, (const float*)Lf, ldl, Lc, n));
+    L64 = Lc;
+    ldl64 = n;
+  }
+  RPID_CHECK(dgemm(ctx, true, true, k, n, k, 1.0, Winv, k, L64, ldl64, 0.0, Z, ldz, o_tmp));
   RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
   if (refine_steps > 0) {
     double* U64 = ws_ptr<double>(ctx, o_U64);
     double* X1 = ws_ptr<double>(ctx, o_X1);
     double* res = ws_ptr<double>(ctx, o_res);
+    double* WU = ws_ptr<double>(ctx, o_WU);
+    double* Pm = ws_ptr<double>(ctx, o_P);
     if (f64) {
       RPID_CHECK(convert_matrix<double, double>(ctx, k, k, (const double*)Uf, ldu, U64, k));
       RPID_CHECK(gather_columns<double, double>(ctx, k, k, (const double*)X, ldx, n, J, X1, k));
@@ -514,17 +529,17 @@ int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64
       RPID_CHECK(convert_matrix<float, double>(ctx, k, k, (const float*)Uf, ldu, U64, k));
       RPID_CHECK(gather_columns<float, double>(ctx, k, k, (const float*)X, ldx, n, J, X1, k));
     }
+    // X_1 = (L_J U')^T, so X_1^{-1} = (W_U W)^T with W_U = U'^{-1}
+    RPID_CHECK(tri_inverse(ctx, k, U64, k, false, false, WU, k));
+    RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, WU, k, Winv, k, 0.0, Pm, k, o_tmp));
     for (int it = 0; it < refine_steps; ++it) {
-      // res = X_k - X_1 Z (FP64, X promoted)
+      // res = X_k - X_1 Z (FP64, X promoted); Z += X_1^{-1} res
       if (f64)
         RPID_CHECK(convert_matrix<double, double>(ctx, k, n, (const double*)X, ldx, res, k));
       else
         RPID_CHECK(convert_matrix<float, double>(ctx, k, n, (const float*)X, ldx, res, k));
       RPID_CHECK(dgemm(ctx, false, false, k, n, k, -1.0, X1, k, Z, ldz, 1.0, res, k, o_tmp));
-      // X_1 d = res with X_1 = (L_J U')^T = U'^T L_J^T: U'^T y = res, then L_J^T d = y
-      RPID_CHECK(tri_solve<double>(ctx, k, n, U64, k, true, true, false, res, 1, k, res, 1, k));
-      RPID_CHECK(tri_solve<double>(ctx, k, n, LJ, k, true, false, true, res, 1, k, res, 1, k));
-      RPID_CHECK(axpy_matrix(ctx, k, n, 1.0, res, k, Z, ldz));
+      RPID_CHECK(dgemm(ctx, true, false, k, n, k, 1.0, Pm, k, res, k, 1.0, Z, ldz, o_tmp));
       RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
     }
   }

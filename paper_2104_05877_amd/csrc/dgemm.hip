@@ -32,73 +32,101 @@ __device__ __forceinline__ double opB(const GemmArgs& a, int64_t k, int64_t j) {
   return a.tb ? a.B[j + k * a.ldb] : a.B[k + j * a.ldb];
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// 64 x 64 output tile per workgroup; 4 waves each own a 32 x 32 quadrant
+// (2 x 2 FP64 MFMA 16x16x4 tiles).  op(A) / op(B) tiles of 16 along K are
+// staged in LDS (transposes resolved while staging), one step ahead.
 __global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs a) {
   __shared__ double As[TK][TM + 1];
   __shared__ double Bs[TK][TN + 1];
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wr = (wid & 1) * 32, wc = (wid >> 1) * 32;
   const int64_t i0 = (int64_t)blockIdx.x * TM;
   const int64_t j0 = (int64_t)blockIdx.y * TN;
   const int64_t kb = (int64_t)blockIdx.z * a.kchunk;
   const int64_t ke = min(a.K, kb + a.kchunk);
-  double acc[4][4] = {};
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{};
+  // Tile loads: each thread fetches 4 elements of op(A) and 4 of op(B) per
+  // K-step; the next step's 8 loads are issued before this step's MFMAs.
+  constexpr int PER = TM * TK / 256;
+  int ai[PER], ak[PER], bj[PER], bk[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u;
+    if (a.ta) {
+      ak[u] = e % TK;
+      ai[u] = e / TK;
+    } else {
+      ai[u] = e % TM;
+      ak[u] = e / TM;
+    }
+    if (a.tb) {
+      bj[u] = e % TN;
+      bk[u] = e / TN;
+    } else {
+      bk[u] = e % TK;
+      bj[u] = e / TK;
+    }
+  }
+  double av_n[PER], bv_n[PER];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int64_t gi = i0 + ai[u], gk = k0 + ak[u];
+      av_n[u] = (gi < a.M && gk < ke) ? opA(a, gi, gk) : 0.0;
+      const int64_t gj = j0 + bj[u], gq = k0 + bk[u];
+      bv_n[u] = (gj < a.N && gq < ke) ? opB(a, gq, gj) : 0.0;
+    }
+  };
+  if (kb < ke) fetch(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += TK) {
-    // load op(A)[i0:i0+64, k0:k0+16] and op(B)[k0:k0+16, j0:j0+64]
-    for (int e = tid; e < TM * TK; e += 256) {
-      int ii, kk;
-      if (a.ta) {
-        kk = e % TK;
-        ii = e / TK;
-      } else {
-        ii = e % TM;
-        kk = e / TM;
-      }
-      const int64_t gi = i0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < a.M && gk < ke) ? opA(a, gi, gk) : 0.0;
-    }
-    for (int e = tid; e < TN * TK; e += 256) {
-      int jj, kk;
-      if (a.tb) {
-        jj = e % TN;
-        kk = e / TN;
-      } else {
-        kk = e % TK;
-        jj = e / TK;
-      }
-      const int64_t gj = j0 + jj, gk = k0 + kk;
-      Bs[kk][jj] = (gj < a.N && gk < ke) ? opB(a, gk, gj) : 0.0;
-    }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[kk][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    for (int u = 0; u < PER; ++u) {
+      As[ak[u]][ai[u]] = av_n[u];
+      Bs[bk[u]][bj[u]] = bv_n[u];
     }
     __syncthreads();
-  }
+    if (k0 + TK < ke) fetch(k0 + TK);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t gi = i0 + ty + 16 * i;
-    if (gi >= a.M) continue;
+    for (int s = 0; s < TK / 4; ++s) {
+      const int kk = s * 4 + (lane >> 4);
+      double pa[2], qb[2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t gj = j0 + tx + 16 * j;
-      if (gj >= a.N) continue;
-      if (a.part_stride) {
-        a.C[(int64_t)blockIdx.z * a.part_stride + gi + gj * a.M] = acc[i][j];
-      } else {
-        double* c = &a.C[gi + gj * a.ldc];
-        *c = a.alpha * acc[i][j] + (a.beta == 0.0 ? 0.0 : a.beta * *c);
-      }
+      for (int x = 0; x < 2; ++x) pa[x] = As[kk][wr + x * 16 + (lane & 15)];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) qb[y] = Bs[kk][wc + y * 16 + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[x], qb[y], acc[x][y], 0, 0, 0);
     }
   }
+  // FP64 MFMA result: register i of lane l is row (l / 16) + 4 i, column l % 16
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t gi = i0 + wr + x * 16 + (lane >> 4) + 4 * i;
+        const int64_t gj = j0 + wc + y * 16 + (lane & 15);
+        if (gi < a.M && gj < a.N) {
+          if (a.part_stride) {
+            a.C[(int64_t)blockIdx.z * a.part_stride + gi + gj * a.M] = acc[x][y][i];
+          } else {
+            double* c = &a.C[gi + gj * a.ldc];
+            *c = a.alpha * acc[x][y][i] + (a.beta == 0.0 ? 0.0 : a.beta * *c);
+          }
+        }
+      }
 }
 
 __global__ void dgemm_reduce_kernel(const double* part, int splits, int64_t stride, int64_t M,

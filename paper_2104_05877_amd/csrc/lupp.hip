@@ -13,19 +13,22 @@
 //  * the column of the current step is mirrored in LDS so that one wave
 //    finds the workgroup's candidate with a 64-lane argmax;
 //  * each step every workgroup publishes its candidate row into a slot and
-//    the candidate's |value| into a per-step word (release, agent scope);
-//    every workgroup polls the G words of the step (acquire), reduces them
-//    identically (largest |value|, ties to the smallest workgroup, which owns
-//    the smallest rows), reads the winning row, and updates its registers.
+//    the candidate's signed value into a per-step word; every workgroup
+//    polls the G words of the step, reduces them identically (largest
+//    |value|, ties to the smallest workgroup, which owns the smallest rows),
+//    reads the winning row, and updates its registers.
+//  * every exchanged word lives in uncached device memory, is written and
+//    read with agent-scope atomics, and carries a tag (launch epoch, step) in
+//    its upper 32 bits: a reader accepts a word only when its tag matches, so
+//    nothing has to be ordered or flushed (an FP64 value travels as two
+//    tagged halves).  Slots alternate between two buffers by step parity, so
+//    a slot is rewritten only after every workgroup has read it.
 //  One device-wide exchange per pivot; no second kernel launch per step.
 #include "rpid_internal.hpp"
 
-#include <hip/hip_cooperative_groups.h>
-
 namespace rpid {
 
-static constexpr uint64_t kSentinel = ~0ull;
-static constexpr unsigned kSpinLimit = 1u << 26;
+static constexpr unsigned kSpinLimit = 1u << 21;  // ~2 s of polling at ~1 us per load
 
 template <typename T>
 struct LuppArgs {
@@ -40,49 +43,82 @@ struct LuppArgs {
   T* Uf;
   int64_t ldu;
   T* diag;
-  uint64_t* slot_val;  // k x G words: |candidate| bits of step t, workgroup g
-  int64_t* slot_idx;   // 2 x G candidate row indices (double buffered)
-  T* slot_row;         // 2 x G x kpad candidate rows (double buffered)
-  unsigned* flags;     // [0] non-finite count, [1] abort
-  int64_t* status;     // 0, t+1 (zero pivot), or a negative RPID_ERR code
+  uint64_t* xval;   // [2][G][W] tagged candidate values
+  uint64_t* xidx;   // [2][G]    tagged candidate row indices
+  uint64_t* xrow;   // [2][G][kpad][W] tagged candidate rows
+  uint64_t* xflag;  // [0] abort (tag = epoch)
+  unsigned epoch;   // 1 .. 2^21 - 1
+  int64_t* status;  // 0, t+1 (zero pivot), or a negative RPID_ERR code
 };
 
 template <typename T>
-__device__ __forceinline__ uint64_t to_bits(T v);
-template <>
-__device__ __forceinline__ uint64_t to_bits<double>(double v) {
-  return (uint64_t)__double_as_longlong(v);
+struct Words {
+  static constexpr int W = sizeof(T) / 4;  // tagged words per value
+};
+
+__device__ __forceinline__ void wstore(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <>
-__device__ __forceinline__ uint64_t to_bits<float>(float v) {
-  return (uint64_t)__float_as_uint(v);
+__device__ __forceinline__ uint64_t wload(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <typename T>
-__device__ __forceinline__ T from_bits(uint64_t b);
-template <>
-__device__ __forceinline__ double from_bits<double>(uint64_t b) {
-  return __longlong_as_double((long long)b);
-}
-template <>
-__device__ __forceinline__ float from_bits<float>(uint64_t b) {
-  return __uint_as_float((unsigned)b);
-}
-template <>
-__device__ __forceinline__ int64_t from_bits<int64_t>(uint64_t b) {
-  return (int64_t)b;
+__device__ __forceinline__ unsigned step_tag(unsigned epoch, int t) {
+  return (epoch << 11) | (unsigned)(t + 1);
 }
 
-template <typename T>
-__device__ __forceinline__ T load_coherent(const T* p) {
-  if constexpr (sizeof(T) == 8) {
-    uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    return from_bits<T>(b);
-  } else {
-    unsigned b = __hip_atomic_load(reinterpret_cast<const unsigned*>(p), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    return from_bits<T>(b);
+__device__ __forceinline__ void put_value(uint64_t* p, float v, unsigned tag) {
+  wstore(p, ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v));
+}
+__device__ __forceinline__ void put_value(uint64_t* p, double v, unsigned tag) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  wstore(p, ((uint64_t)tag << 32) | (b >> 32));
+  wstore(p + 1, ((uint64_t)tag << 32) | (b & 0xffffffffull));
+}
+__device__ __forceinline__ bool try_value(const uint64_t* p, unsigned tag, float& v) {
+  const uint64_t w = wload(p);
+  if ((unsigned)(w >> 32) != tag) return false;
+  v = __uint_as_float((unsigned)w);
+  return true;
+}
+__device__ __forceinline__ bool try_value(const uint64_t* p, unsigned tag, double& v) {
+  const uint64_t w0 = wload(p), w1 = wload(p + 1);
+  if ((unsigned)(w0 >> 32) != tag || (unsigned)(w1 >> 32) != tag) return false;
+  v = __longlong_as_double((long long)((w0 << 32) | (w1 & 0xffffffffull)));
+  return true;
+}
+
+// Spin until the tagged word(s) at p carry `tag`; false if the launch was
+// aborted (another workgroup timed out) or this wait exceeded the spin limit.
+template <typename V>
+__device__ __forceinline__ bool wait_value(const uint64_t* p, unsigned tag, V& v, uint64_t* xflag,
+                                           unsigned epoch) {
+  unsigned spins = 0;
+  while (!try_value(p, tag, v)) {
+    if ((++spins & 255u) == 0) {
+      if ((unsigned)wload(xflag) == epoch || spins > kSpinLimit) {
+        wstore(xflag, (uint64_t)epoch);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
   }
+  return true;
+}
+__device__ __forceinline__ bool wait_index(const uint64_t* p, unsigned tag, int64_t& idx,
+                                           uint64_t* xflag, unsigned epoch) {
+  unsigned spins = 0;
+  uint64_t w;
+  while ((unsigned)((w = wload(p)) >> 32) != tag) {
+    if ((++spins & 255u) == 0) {
+      if ((unsigned)wload(xflag) == epoch || spins > kSpinLimit) {
+        wstore(xflag, (uint64_t)epoch);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  idx = (int64_t)(int)(unsigned)w;
+  return true;
 }
 
 // (value, index) argmax across a 64-lane wave: larger value wins, ties go to
@@ -101,6 +137,7 @@ __device__ __forceinline__ void wave_argmax(T& v, int& i) {
 
 template <typename T, int R, int NTMAX>
 __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
+  constexpr int W = Words<T>::W;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int g = blockIdx.x;
@@ -110,17 +147,16 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
   const int lane = tid & 63;
   const int wid = tid >> 6;
 
-  __shared__ T colbuf[R];      // column of the current step, this workgroup's rows
-  __shared__ T mult[R];        // multipliers of the current step (0 for frozen rows)
-  __shared__ int alive[R];     // 1 while the row has not been chosen as a pivot
-  __shared__ T red_v[16];
-  __shared__ int red_i[16];
+  __shared__ T colbuf[R];   // column of the current step, this workgroup's rows
+  __shared__ T mult[R];     // multipliers of the current step (0 for frozen rows)
+  __shared__ int alive[R];  // 1 while the row has not been chosen as a pivot
   __shared__ int sh_bq;
   __shared__ T sh_best;
   __shared__ int sh_gw;
-  __shared__ T sh_gbest;
-  __shared__ int sh_stop;
-  __shared__ int sh_nonfinite;
+  __shared__ T sh_pv;
+  __shared__ int sh_code;   // 0 go on, 1 stop: status in sh_status
+  __shared__ int64_t sh_status;
+  __shared__ int sh_abort;
 
   // ---- load this workgroup's rows of the panel into registers ------------
   T s[R];
@@ -139,14 +175,19 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
   if (tid == 0) {
 #pragma unroll
     for (int q = 0; q < R; ++q) colbuf[q] = s[q];
+    sh_abort = 0;
   }
-  if (__any(bad) && lane == 0) atomicAdd(&a.flags[0], 1u);
+  // a non-finite entry anywhere in the slab is published as a NaN candidate
+  __shared__ int sh_bad;
+  if (tid == 0) sh_bad = 0;
+  __syncthreads();
+  if (__any(bad) && lane == 0) sh_bad = 1;
   __syncthreads();
 
-  int t = 0;
   int64_t final_status = 0;
-  for (; t < k; ++t) {
+  for (int t = 0; t < k; ++t) {
     const int par = t & 1;
+    const unsigned tag = step_tag(a.epoch, t);
     // ---- (1) candidate of this workgroup: one wave over the LDS column ----
     if (wid == 0) {
       T bv = T(-2);
@@ -163,119 +204,106 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       wave_argmax(bv, bi);
       if (lane == 0) {
         sh_bq = bi;
-        sh_best = bv;
-        sh_stop = 0;
+        T best = (bi < R) ? colbuf[bi] : T(0);  // signed candidate (0: none left)
+        if (t == 0 && sh_bad) best = T(NAN);
+        sh_best = best;
       }
     }
     __syncthreads();
     const int bq = sh_bq;
 
-    // ---- (2) publish the candidate row and its |value| --------------------
-    T* myrow = a.slot_row + ((size_t)par * G + g) * a.kpad;
-    if (tid >= t && tid < k) {
+    // ---- (2) publish: candidate row, index and value (tagged words) -------
+    uint64_t* myrow = a.xrow + ((size_t)par * G + g) * a.kpad * W;
+    if (tid > t && tid < k) {
       T v = T(0);
 #pragma unroll
       for (int q = 0; q < R; ++q) v = (q == bq) ? s[q] : v;
-      myrow[tid] = v;
+      put_value(myrow + (size_t)tid * W, v, tag);
     }
-    if (tid == 0) a.slot_idx[par * G + g] = (bq < R) ? row0 + bq : -1;
-    __syncthreads();
     if (tid == 0) {
-      __threadfence();
-      const T pub = (bq < R) ? sh_best : T(-1);
-      __hip_atomic_store(&a.slot_val[(size_t)t * G + g], to_bits<T>(pub), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      wstore(&a.xidx[par * G + g],
+             ((uint64_t)tag << 32) | (uint64_t)(unsigned)(int)((bq < R) ? row0 + bq : -1));
+      put_value(&a.xval[((size_t)par * G + g) * W], sh_best, tag);
     }
 
-    // ---- (3) wait for every workgroup's word of step t, reduce ------------
-    T cv = T(-2);
-    int ci = 0x7fffffff;
-    for (int i = tid; i < G; i += nt) {
-      uint64_t b;
-      unsigned spins = 0;
-      while (true) {
-        b = __hip_atomic_load(&a.slot_val[(size_t)t * G + i], __ATOMIC_ACQUIRE,
-                              __HIP_MEMORY_SCOPE_AGENT);
-        if (b != kSentinel) break;
-        if ((++spins & 255u) == 0) {
-          if (__hip_atomic_load(&a.flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-              spins > kSpinLimit) {
-            __hip_atomic_store(&a.flags[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sh_stop = 1;
-            break;
+    // ---- (3) wave 0 gathers every workgroup's value and reduces ------------
+    if (wid == 0) {
+      T cv = T(-2), cpv = T(0);
+      int ci = 0x7fffffff;
+      bool ok = true, nonfinite = false;
+      for (int i = lane; i < G && ok; i += 64) {
+        T v;
+        ok = wait_value(&a.xval[((size_t)par * G + i) * W], tag, v, a.xflag, a.epoch);
+        if (ok) {
+          if (!isfinite(v)) nonfinite = true;
+          const T av = fabs(v);
+          if (av > cv || (av == cv && i < ci)) {
+            cv = av;
+            ci = i;
+            cpv = v;
           }
         }
-        __builtin_amdgcn_s_sleep(1);
       }
-      if (b != kSentinel) {
-        const T v = from_bits<T>(b);
-        if (v > cv || (v == cv && i < ci)) {
-          cv = v;
-          ci = i;
+      const bool any_fail = __any(!ok);
+      const bool any_nf = __any(nonfinite);
+      wave_argmax(cv, ci);
+      if (lane == 0) {
+        sh_gw = ci;
+        sh_code = 0;
+        if (any_fail) {
+          sh_code = 1;
+          sh_status = RPID_ERR_TIMEOUT;
+        } else if (any_nf) {
+          sh_code = 1;
+          sh_status = RPID_ERR_NONFINITE;
+        } else if (!(cv > T(0))) {  // exactly zero pivot (or no candidate left)
+          sh_code = 1;
+          sh_status = t + 1;
         }
       }
     }
-    wave_argmax(cv, ci);
-    if (lane == 0) {
-      red_v[wid] = cv;
-      red_i[wid] = ci;
-    }
     __syncthreads();
-    if (sh_stop) {
-      final_status = RPID_ERR_TIMEOUT;
-      break;
-    }
-    if (wid == 0) {
-      const int nw = nt >> 6;
-      T v = (lane < nw) ? red_v[lane] : T(-2);
-      int i = (lane < nw) ? red_i[lane] : 0x7fffffff;
-      wave_argmax(v, i);
-      if (lane == 0) {
-        sh_gw = i;
-        sh_gbest = v;
-        sh_nonfinite = (t == 0) ? (int)__hip_atomic_load(&a.flags[0], __ATOMIC_ACQUIRE,
-                                                          __HIP_MEMORY_SCOPE_AGENT)
-                                : 0;
-      }
-    }
-    __syncthreads();
-    if (sh_nonfinite != 0) {
-      final_status = RPID_ERR_NONFINITE;
+    if (sh_code) {
+      final_status = sh_status;
       break;
     }
     const int gw = sh_gw;
-    const T gbest = sh_gbest;
-    if (!(gbest > T(0))) {  // exactly zero pivot (or no candidate left)
-      final_status = t + 1;
+
+    // ---- (4) the pivot: value, row index and row of the winner -------------
+    bool ok = true;
+    T pv;
+    ok = wait_value(&a.xval[((size_t)par * G + gw) * W], tag, pv, a.xflag, a.epoch);
+    int64_t prow = -1;
+    if (ok) ok = wait_index(&a.xidx[par * G + gw], tag, prow, a.xflag, a.epoch);
+    T uj = T(0);
+    if (ok && tid > t && tid < k)
+      ok = wait_value(a.xrow + (((size_t)par * G + gw) * a.kpad + tid) * W, tag, uj, a.xflag,
+                      a.epoch);
+    if (!ok) sh_abort = 1;
+    if (ok) {
+      // multipliers (one per row, coalesced L writes); the pivot row gets 1
+      for (int q = tid; q < R; q += nt) {
+        const int64_t row = row0 + q;
+        const bool live = alive[q] && row != prow;
+        const T mq = live ? colbuf[q] / pv : T(0);
+        mult[q] = mq;
+        if (row < a.n) a.Lf[row + (int64_t)t * a.ldl] = live ? mq : (row == prow ? T(1) : T(0));
+      }
+      if (g == 0) {
+        if (tid == 0) {
+          a.J[t] = prow;
+          if (a.diag) a.diag[t] = fabs(pv);
+        }
+        if (tid < k) a.Uf[t + (int64_t)tid * a.ldu] = (tid > t) ? uj : (tid == t ? pv : T(0));
+      }
+    }
+    __syncthreads();
+    if (sh_abort) {
+      final_status = RPID_ERR_TIMEOUT;
       break;
     }
 
-    // ---- (4) read the pivot row, record outputs ----------------------------
-    const T* wrow = a.slot_row + ((size_t)par * G + gw) * a.kpad;
-    const int64_t prow = load_coherent(&a.slot_idx[par * G + gw]);
-    const T pv = load_coherent(&wrow[t]);
-    T uj = T(0);
-    if (tid > t && tid < k) uj = load_coherent(&wrow[tid]);
-    if (g == gw && tid == 0) alive[prow - row0] = 0;
-    if (g == 0) {
-      if (tid == 0) {
-        a.J[t] = prow;
-        if (a.diag) a.diag[t] = fabs(pv);
-      }
-      if (tid < k) a.Uf[t + (int64_t)tid * a.ldu] = (tid >= t) ? load_coherent(&wrow[tid]) : T(0);
-    }
-    __syncthreads();
-
-    // ---- (5) multipliers (one per row, coalesced L writes) -----------------
-    for (int q = tid; q < R; q += nt) {
-      const int64_t row = row0 + q;
-      const T mq = alive[q] ? colbuf[q] / pv : T(0);
-      mult[q] = mq;
-      if (row < a.n) a.Lf[row + (int64_t)t * a.ldl] = alive[q] ? mq : (row == prow ? T(1) : T(0));
-    }
-    __syncthreads();
-
-    // ---- (6) Schur update of this workgroup's rows, columns t+1..k-1 -------
+    // ---- (5) Schur update of this workgroup's rows, columns t+1..k-1 -------
     if (tid > t && tid < k) {
 #pragma unroll
       for (int q = 0; q < R; ++q) s[q] = fma(-mult[q], uj, s[q]);
@@ -284,21 +312,19 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
         for (int q = 0; q < R; ++q) colbuf[q] = s[q];
       }
     }
+    if (g == gw && tid == 0) alive[prow - row0] = 0;
     __syncthreads();
   }
   if (g == 0 && tid == 0) *a.status = final_status;
 }
 
 size_t lupp_workspace_bytes(rpid_ctx ctx, int64_t n, int64_t k, int elem_bytes) {
+  // the exchange slots live in the context's uncached buffer
   (void)ctx;
-  const int64_t G = (n + 15) / 16;  // upper bound (smallest R)
-  const int64_t kpad = (k + 63) / 64 * 64;
-  size_t b = 0;
-  b += (size_t)k * G * 8 + 256;
-  b += (size_t)2 * G * 8 + 256;
-  b += (size_t)2 * G * kpad * elem_bytes + 256;
-  b += 256;
-  return b;
+  (void)n;
+  (void)k;
+  (void)elem_bytes;
+  return 256;
 }
 
 __global__ void fill_u64_kernel(uint64_t* p, size_t count, uint64_t value) {
@@ -380,13 +406,31 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   const int G = (int)G64;
   const int kpad = nt;
 
+  (void)ws_off;
+  constexpr int W = Words<T>::W;
   Carve cv;
-  cv.off = ws_off;
-  size_t o_val = cv.take<uint64_t>((size_t)k * G);
-  size_t o_idx = cv.take<int64_t>((size_t)2 * G);
-  size_t o_row = cv.take<T>((size_t)2 * G * kpad);
-  size_t o_flags = cv.take<uint64_t>(1);
-  RPID_CHECK(ws_check(ctx, cv.off));
+  const size_t o_val = cv.take<uint64_t>((size_t)2 * G * W);
+  const size_t o_idx = cv.take<uint64_t>((size_t)2 * G);
+  const size_t o_row = cv.take<uint64_t>((size_t)2 * G * kpad * W);
+  const size_t o_flag = cv.take<uint64_t>(1);
+  bool fresh = false;
+  if (cv.off > ctx->uc_bytes) {
+    // the previous buffer (if any) is left allocated on purpose
+    size_t want = cv.off < ((size_t)4 << 20) ? ((size_t)4 << 20) : cv.off;
+    void* p = nullptr;
+    if (hipExtMallocWithFlags(&p, want, hipDeviceMallocUncached) != hipSuccess) return RPID_ERR_NOMEM;
+    ctx->uc = p;
+    ctx->uc_bytes = want;
+    fresh = true;
+  }
+  // launch epoch (21 bits) tags every exchanged word; tag 0 never matches
+  if (++ctx->lupp_epoch >= (1u << 21)) {
+    ctx->lupp_epoch = 1;
+    fresh = true;
+  }
+  if (fresh)
+    RPID_CHECK(launch_fill_u64(ctx, static_cast<uint64_t*>(ctx->uc), ctx->uc_bytes / 8, 0ull));
+  char* ucb = static_cast<char*>(ctx->uc);
 
   LuppArgs<T> a;
   a.base = base;
@@ -401,14 +445,12 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   a.Uf = Uf;
   a.ldu = ldu;
   a.diag = diag;
-  a.slot_val = ws_ptr<uint64_t>(ctx, o_val);
-  a.slot_idx = ws_ptr<int64_t>(ctx, o_idx);
-  a.slot_row = ws_ptr<T>(ctx, o_row);
-  a.flags = ws_ptr<unsigned>(ctx, o_flags);
+  a.xval = reinterpret_cast<uint64_t*>(ucb + o_val);
+  a.xidx = reinterpret_cast<uint64_t*>(ucb + o_idx);
+  a.xrow = reinterpret_cast<uint64_t*>(ucb + o_row);
+  a.xflag = reinterpret_cast<uint64_t*>(ucb + o_flag);
+  a.epoch = ctx->lupp_epoch;
   a.status = status_dev;
-
-  RPID_CHECK(launch_fill_u64(ctx, a.slot_val, (size_t)k * G, kSentinel));
-  RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(a.flags), 1, 0ull));
   if (ntmax == 256) return dispatch_R<T, 256>(ctx, a, R, G, nt);
   if (ntmax == 512) return dispatch_R<T, 512>(ctx, a, R, G, nt);
   return dispatch_R<T, 1024>(ctx, a, R, G, nt);

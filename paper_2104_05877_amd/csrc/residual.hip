@@ -41,17 +41,31 @@ __global__ __launch_bounds__(256) void residual_f64_kernel(int64_t m, int64_t n,
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4d{};
-  for (int64_t k0 = 0; k0 < r; k0 += BK) {
-    __syncthreads();
-    for (int e = tid; e < 64 * BK; e += 256) {
+  // 4 elements of each operand per thread per K-step, fetched one step ahead
+  double pn[4], qn[4];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
       const int ii = e % 64, kk = e / 64;
       const int64_t gi = i0 + ii, gk = k0 + kk;
-      Ps[kk][ii] = (gi < m && gk < r) ? P[gi + gk * ldp] : 0.0;
+      pn[u] = (gi < m && gk < r) ? P[gi + gk * ldp] : 0.0;
       const int jj = e / BK, kq = e % BK;
       const int64_t gj = j0 + jj, gq = k0 + kq;
-      Qs[kq][jj] = (gj < n && gq < r) ? Q[gq + gj * ldq] : 0.0;
+      qn[u] = (gj < n && gq < r) ? Q[gq + gj * ldq] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < r; k0 += BK) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u;
+      Ps[e / 64][e % 64] = pn[u];
+      Qs[e % BK][e / BK] = qn[u];
     }
     __syncthreads();
+    if (k0 + BK < r) fetch(k0 + BK);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int kk = s * 4 + (lane >> 4);
@@ -104,41 +118,70 @@ __global__ __launch_bounds__(256) void residual_f64_kernel(int64_t m, int64_t n,
 
 // ---------------------------------------------------------------------------
 // BF16 form.  Workgroup tile 128 x 128 (4 waves, each 64 x 64 = 4 x 4 MFMA
-// tiles of 16x16x32), K staged 32 at a time in LDS.
+// tiles of 16x16x32), K staged 32 at a time in LDS.  Both operands arrive
+// k-contiguous: Pt is r x m column-major (row i of P is Pt(:, i)) and Q is
+// r x n column-major, so every 8 consecutive k of one row/column are one
+// 16-byte load.  The next K-step's tiles are prefetched into registers
+// while the current one is multiplied.
 // ---------------------------------------------------------------------------
+constexpr int RB_BK = 32;
+constexpr int RB_PAD = RB_BK + 8;  // 80-byte LDS rows: 16-byte aligned, banks spread
+
+__device__ __forceinline__ uint4 load8_bf16(const uint16_t* base, int64_t ld, int64_t row,
+                                            int64_t nrows, int64_t k, int64_t r, bool vec_ok) {
+  // elements k..k+7 of column `row` of a (r x nrows, ld) k-contiguous matrix
+  uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  if (row >= nrows) return v;
+  const uint16_t* p = base + row * ld + k;
+  if (vec_ok && k + 8 <= r) return *reinterpret_cast<const uint4*>(p);
+  uint16_t t[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) t[e] = (k + e < r) ? p[e] : (uint16_t)0;
+  __builtin_memcpy(&v, t, 16);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void residual_bf16_kernel(int64_t m, int64_t n, int64_t r,
                                                             const uint16_t* A, int64_t lda,
-                                                            const uint16_t* P, int64_t ldp,
+                                                            const uint16_t* Pt, int64_t ldpt,
                                                             const uint16_t* Q, int64_t ldq,
                                                             double* partials) {
-  constexpr int BK = 32;
-  constexpr int PADK = BK + 8;  // 80-byte rows: 16-byte aligned, spreads banks
-  __shared__ __attribute__((aligned(16))) uint16_t Ps[128][PADK];  // Ps[row][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Qs[128][PADK];  // Qs[col][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Ps[128][RB_PAD];  // Ps[row][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Qs[128][RB_PAD];  // Qs[col][k]
   __shared__ double red[2][4];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * 128, j0 = (int64_t)blockIdx.y * 128;
   const int wr = (wid & 1) * 64, wc = (wid >> 1) * 64;
+  const bool vec_ok = ((uintptr_t)Pt % 16 == 0) && ((uintptr_t)Q % 16 == 0) && (ldpt % 8 == 0) &&
+                      (ldq % 8 == 0);
+  // each thread moves 2 vectors of P and 2 of Q per K-step: (row, k-octet)
+  const int lr0 = tid >> 2, lk0 = (tid & 3) * 8;  // rows 0..63, then +64
   v4f acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4f{};
-  for (int64_t k0 = 0; k0 < r; k0 += BK) {
+  uint4 pv[2], qv[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    pv[h] = load8_bf16(Pt, ldpt, i0 + lr0 + 64 * h, m, lk0, r, vec_ok);
+    qv[h] = load8_bf16(Q, ldq, j0 + lr0 + 64 * h, n, lk0, r, vec_ok);
+  }
+  for (int64_t k0 = 0; k0 < r; k0 += RB_BK) {
     __syncthreads();
-    // P tile: 128 rows x 32 k, P column-major (rows contiguous)
-    for (int e = tid; e < 128 * BK; e += 256) {
-      const int ii = e % 128, kk = e / 128;
-      const int64_t gi = i0 + ii, gk = k0 + kk;
-      Ps[ii][kk] = (gi < m && gk < r) ? P[gi + gk * ldp] : (uint16_t)0;
-    }
-    // Q tile: 32 k x 128 cols, Q column-major (k contiguous)
-    for (int e = tid; e < 128 * BK; e += 256) {
-      const int kk = e % BK, jj = e / BK;
-      const int64_t gj = j0 + jj, gk = k0 + kk;
-      Qs[jj][kk] = (gj < n && gk < r) ? Q[gk + gj * ldq] : (uint16_t)0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<uint4*>(&Ps[lr0 + 64 * h][lk0]) = pv[h];
+      *reinterpret_cast<uint4*>(&Qs[lr0 + 64 * h][lk0]) = qv[h];
     }
     __syncthreads();
+    if (k0 + RB_BK < r) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        pv[h] = load8_bf16(Pt, ldpt, i0 + lr0 + 64 * h, m, k0 + RB_BK + lk0, r, vec_ok);
+        qv[h] = load8_bf16(Q, ldq, j0 + lr0 + 64 * h, n, k0 + RB_BK + lk0, r, vec_ok);
+      }
+    }
     v8bf pa[4], qb[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -182,6 +225,39 @@ __global__ __launch_bounds__(256) void residual_bf16_kernel(int64_t m, int64_t n
     const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     partials[2 * b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     partials[2 * b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// Pt((c + p k), i) = A(i, J[c]) for every term p (BF16 skeleton columns,
+// replicated once per term of the other factor).
+__global__ void pack_cols_t_kernel(int64_t m, int64_t k, int parts, const uint16_t* A,
+                                   int64_t lda, int64_t ncols, const int64_t* J, uint16_t* Pt) {
+  const int64_t rr = (int64_t)parts * k;
+  const int64_t total = m * rr;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e % k, i = (e / k) % m, p = e / (k * m);
+    (void)p;
+    const int64_t j = J[c];
+    const uint16_t v = (j >= 0 && j < ncols) ? A[i + j * lda] : (uint16_t)0;
+    Pt[(c + p * k) + i * rr] = v;
+  }
+}
+
+// Pt((c + p k), i) = term p of the BF16 split of P(i, c) (P FP64 m x k).
+__global__ void pack_split_t_kernel(int64_t m, int64_t k, int parts, const double* P,
+                                    int64_t ldp, uint16_t* Pt) {
+  const int64_t rr = (int64_t)parts * k;
+  const int64_t total = m * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e % k, i = e / k;
+    double v = P[i + c * ldp];
+    for (int p = 0; p < parts; ++p) {
+      const uint16_t b = float_to_bf16_bits((float)v);
+      Pt[(c + p * k) + i * rr] = b;
+      v -= (double)bf16_bits_to_float(b);
+    }
   }
 }
 
@@ -233,14 +309,30 @@ int residual_f64(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const TA* A, int
 }
 
 int residual_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* A, int64_t lda,
-                  const uint16_t* P, int64_t ldp, const uint16_t* Q, int64_t ldq,
+                  const uint16_t* Pt, int64_t ldpt, const uint16_t* Q, int64_t ldq,
                   double* partials, double* out2) {
   dim3 grid((unsigned)((m + 127) / 128), (unsigned)((n + 127) / 128));
-  hipLaunchKernelGGL(residual_bf16_kernel, grid, dim3(256), 0, ctx->stream, m, n, r, A, lda, P,
-                     ldp, Q, ldq, partials);
+  hipLaunchKernelGGL(residual_bf16_kernel, grid, dim3(256), 0, ctx->stream, m, n, r, A, lda, Pt,
+                     ldpt, Q, ldq, partials);
   RPID_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(partial_sum_kernel, dim3(1), dim3(1024), 0, ctx->stream, partials,
                      (int64_t)grid.x * grid.y, out2);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+
+int pack_cols_t(rpid_ctx ctx, int64_t m, int64_t k, int parts, const uint16_t* A, int64_t lda,
+                int64_t ncols, const int64_t* J, uint16_t* Pt) {
+  hipLaunchKernelGGL(pack_cols_t_kernel, dim3(4096), dim3(256), 0, ctx->stream, m, k, parts, A,
+                     lda, ncols, J, Pt);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+
+int pack_split_t(rpid_ctx ctx, int64_t m, int64_t k, int parts, const double* P, int64_t ldp,
+                 uint16_t* Pt) {
+  hipLaunchKernelGGL(pack_split_t_kernel, dim3(4096), dim3(256), 0, ctx->stream, m, k, parts, P,
+                     ldp, Pt);
   RPID_HIP_CHECK(hipGetLastError());
   return RPID_OK;
 }

@@ -17,6 +17,12 @@ struct rpid_ctx_s {
   size_t ws_bytes = 0;
   // Pinned host word for status read-back.
   int64_t* host_status = nullptr;
+  // Uncached device memory for the cross-workgroup exchange of the LUPP
+  // kernel.  Once a kernel has read it, it stays allocated until the process
+  // ends (a grown buffer replaces, but does not free, the previous one).
+  void* uc = nullptr;
+  size_t uc_bytes = 0;
+  unsigned lupp_epoch = 0;  // tag of the LUPP exchange words of the latest launch
 };
 
 namespace rpid {
@@ -125,6 +131,10 @@ template <typename TB>
 int tri_solve(rpid_ctx ctx, int64_t k, int64_t nrhs, const double* T, int64_t ldt, bool trans,
               bool lower_op, bool unit, const TB* B, int64_t brs, int64_t bcs, double* X,
               int64_t xrs, int64_t xcs);
+
+// W = T^{-1} for a k x k triangular T (k <= 512), lower or upper, unit or not.
+int tri_inverse(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, bool lower, bool unit,
+                double* W, int64_t ldw);
 
 // Cholesky G = R^T R of `batch` SPD k x k matrices (in place, upper R; the
 // strict lower part is zeroed), one workgroup per matrix.  status[b] = 0 or

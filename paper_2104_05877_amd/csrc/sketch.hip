@@ -243,6 +243,135 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchArgs<TE> a) {
   }
 }
 
+// Fast path (aligned operands, every K-range a whole number of BK stages):
+// the same tiling, software-pipelined -- while stage s is multiplied, the
+// Omega vectors and A fragments of stage s+1 are already in flight into
+// registers; staging has no per-element branches.
+template <typename TE, int RT>
+__global__ __launch_bounds__(256) void sketch_fast_kernel(SketchArgs<TE> a) {
+  using M = MT<TE>;
+  using AccV = typename M::AccV;
+  constexpr int VEC = M::VEC;
+  constexpr int BK = M::BK;
+  constexpr int CT = M::CT;
+  constexpr int SUB = BK / (4 * VEC);
+  constexpr int EPV = 16 / (int)sizeof(TE);     // elements per 16-byte vector
+  constexpr int VPR = BK / EPV;                 // vectors per LDS row
+  constexpr int ROWS = 16 * RT;
+  constexpr int NV = (ROWS * VPR + 255) / 256;  // Omega vectors per thread per stage
+  constexpr int LROW = BK + 16 / (int)sizeof(TE) * 2;
+
+  __shared__ __attribute__((aligned(16))) TE lds[ROWS * LROW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int q = lane >> 4;
+  const int c16 = lane & 15;
+  const int bid = blockIdx.x;
+  const int split_id = bid % a.split;
+  const int rest = bid / a.split;
+  const int64_t ncolstrips = (a.n + 4 * CT * 16 - 1) / (4 * CT * 16);
+  const int strip = (int)(rest % ncolstrips);
+  const int lchunk = (int)(rest / ncolstrips);
+  const int row_base = lchunk * ROWS;
+  const int rt_act = min(RT, (a.l - row_base + 15) / 16);
+  const int64_t kbeg = (int64_t)split_id * a.kchunk;
+  const int64_t kend = min(a.m, kbeg + a.kchunk);
+  const int nst = (int)((kend - kbeg) / BK);
+  const int64_t col_base = (int64_t)strip * (4 * CT * 16) + wid * (CT * 16);
+
+  // per-thread Omega vector slots: (row, k-offset) and validity
+  const TE* optr[NV];
+  int lofs[NV];
+  bool oval[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int idx = tid + 256 * v;
+    const int r = idx / VPR;
+    const int kk = (idx % VPR) * EPV;
+    const int grow = row_base + r;
+    oval[v] = (idx < ROWS * VPR) && (grow < a.l);
+    optr[v] = a.Pt + (int64_t)(oval[v] ? grow : 0) * a.ldp + kbeg + kk;
+    lofs[v] = (idx < ROWS * VPR) ? r * LROW + kk : -1;
+  }
+  // per-lane A column pointers (columns past n read column 0 and are dropped)
+  const TE* aptr[CT];
+  bool cval[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int64_t col = col_base + c * 16 + c16;
+    cval[c] = col < a.n;
+    aptr[c] = a.A + (cval[c] ? col : 0) * a.lda + kbeg + q * VEC;
+  }
+
+  AccV acc[RT][CT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[r][c] = AccV{};
+
+  uint4 ov[NV];
+  Frag<TE> bf[SUB][CT];
+  auto fetch = [&](int st) {
+    const int64_t ko = (int64_t)st * BK;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      ov[v] = oval[v] ? *reinterpret_cast<const uint4*>(optr[v] + ko) : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) load_frag(bf[sub][c], aptr[c] + ko + sub * 4 * VEC);
+  };
+
+  if (nst > 0) fetch(0);
+  for (int st = 0; st < nst; ++st) {
+    __syncthreads();  // the previous stage's LDS reads are done
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (lofs[v] >= 0) *reinterpret_cast<uint4*>(&lds[lofs[v]]) = ov[v];
+    Frag<TE> cur[SUB][CT];
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) cur[sub][c] = bf[sub][c];
+    __syncthreads();
+    if (st + 1 < nst) fetch(st + 1);
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        if (r < rt_act) {
+          Frag<TE> af;
+          load_frag(af, &lds[(r * 16 + c16) * LROW + sub * 4 * VEC + q * VEC]);
+#pragma unroll
+          for (int s = 0; s < VEC / M::KMFMA; ++s)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[r][c] = mfma_step<TE>(af, cur[sub][c], s, acc[r][c]);
+        }
+      }
+    }
+  }
+
+  typename M::Acc* out = a.out + (int64_t)split_id * a.out_split_stride;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    if (r < rt_act) {
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int64_t col = col_base + c * 16 + c16;
+        if (cval[c]) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = row_base + r * 16 + M::out_row(q, i);
+            if (row < a.l) out[row + col * a.ldo] = acc[r][c][i];
+          }
+        }
+      }
+    }
+  }
+}
+
 // X(r, j) = sum_s part[s](r, j) in a fixed order, converted to the X type.
 template <typename TA, typename TX>
 __global__ void split_reduce_kernel(const TA* part, int split, int64_t stride, int64_t l,
@@ -269,9 +398,10 @@ static int sketch_impl(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int
   const int ltiles = (int)((l + 15) / 16);
   const int64_t colw = 4 * M::CT * 16;
   const int64_t strips = (n + colw - 1) / colw;
-  // Split K so that the grid holds about two workgroups per CU.
+  // Split K so that the grid fills the chip in one round (one workgroup per
+  // CU: the tile holds 204+ accumulator registers per lane).
   const int64_t base_wgs = strips * lchunks;
-  int64_t split = (2 * (int64_t)ctx->num_cu + base_wgs - 1) / base_wgs;
+  int64_t split = (int64_t)ctx->num_cu / base_wgs;
   const int64_t kblocks = (m + M::BK - 1) / M::BK;
   if (split > kblocks) split = kblocks;
   if (split > 16) split = 16;
@@ -308,7 +438,10 @@ static int sketch_impl(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int
     a.out_split_stride = l * n;
   }
   const int64_t grid = split * strips * lchunks;
-  if (aligned)
+  if (aligned && m % M::BK == 0)
+    hipLaunchKernelGGL((sketch_fast_kernel<TE, RT>), dim3((unsigned)grid), dim3(256), 0,
+                       ctx->stream, a);
+  else if (aligned)
     hipLaunchKernelGGL((sketch_kernel<TE, RT, true>), dim3((unsigned)grid), dim3(256), 0,
                        ctx->stream, a);
   else
