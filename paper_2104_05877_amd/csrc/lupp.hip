@@ -13,10 +13,14 @@
 //  * the column of the current step is mirrored in LDS so that one wave
 //    finds the workgroup's candidate with a 64-lane argmax;
 //  * each step every workgroup publishes its candidate row into a slot and
-//    the candidate's signed value into a per-step word; every workgroup
-//    polls the G words of the step, reduces them identically (largest
-//    |value|, ties to the smallest workgroup, which owns the smallest rows),
-//    reads the winning row, and updates its registers.
+//    the candidate's signed value into a per-step word; one wave of every
+//    workgroup polls the G words of the step and reduces them identically
+//    (largest |value|, ties to the smallest workgroup, which owns the
+//    smallest rows), so every workgroup knows the winner and the pivot value
+//    without a further exchange; thread j then reads word j of the winning
+//    row (distinct addresses) while the multipliers are formed, and the
+//    winning workgroup writes J, the pivot and row t of U from its own
+//    registers.
 //  * every exchanged word lives in uncached device memory, is written and
 //    read with agent-scope atomics, and carries a tag (launch epoch, step) in
 //    its upper 32 bits: a reader accepts a word only when its tag matches, so
@@ -44,7 +48,6 @@ struct LuppArgs {
   int64_t ldu;
   T* diag;
   uint64_t* xval;   // [2][G][W] tagged candidate values
-  uint64_t* xidx;   // [2][G]    tagged candidate row indices
   uint64_t* xrow;   // [2][G][kpad][W] tagged candidate rows
   uint64_t* xflag;  // [0] abort (tag = epoch)
   unsigned epoch;   // 1 .. 2^21 - 1
@@ -104,23 +107,6 @@ __device__ __forceinline__ bool wait_value(const uint64_t* p, unsigned tag, V& v
   }
   return true;
 }
-__device__ __forceinline__ bool wait_index(const uint64_t* p, unsigned tag, int64_t& idx,
-                                           uint64_t* xflag, unsigned epoch) {
-  unsigned spins = 0;
-  uint64_t w;
-  while ((unsigned)((w = wload(p)) >> 32) != tag) {
-    if ((++spins & 255u) == 0) {
-      if ((unsigned)wload(xflag) == epoch || spins > kSpinLimit) {
-        wstore(xflag, (uint64_t)epoch);
-        return false;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-  idx = (int64_t)(int)(unsigned)w;
-  return true;
-}
-
 // (value, index) argmax across a 64-lane wave: larger value wins, ties go to
 // the smaller index.  Invalid entries carry value -2 (never a modulus).
 template <typename T>
@@ -212,19 +198,15 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     __syncthreads();
     const int bq = sh_bq;
 
-    // ---- (2) publish: candidate row, index and value (tagged words) -------
+    // ---- (2) publish: candidate row and value (tagged words) ---------------
     uint64_t* myrow = a.xrow + ((size_t)par * G + g) * a.kpad * W;
-    if (tid > t && tid < k) {
-      T v = T(0);
+    T myv = T(0);  // this thread's column of the candidate row
+    if (tid >= t && tid < k) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) v = (q == bq) ? s[q] : v;
-      put_value(myrow + (size_t)tid * W, v, tag);
+      for (int q = 0; q < R; ++q) myv = (q == bq) ? s[q] : myv;
+      if (tid > t) put_value(myrow + (size_t)tid * W, myv, tag);
     }
-    if (tid == 0) {
-      wstore(&a.xidx[par * G + g],
-             ((uint64_t)tag << 32) | (uint64_t)(unsigned)(int)((bq < R) ? row0 + bq : -1));
-      put_value(&a.xval[((size_t)par * G + g) * W], sh_best, tag);
-    }
+    if (tid == 0) put_value(&a.xval[((size_t)par * G + g) * W], sh_best, tag);
 
     // ---- (3) wave 0 gathers every workgroup's value and reduces ------------
     if (wid == 0) {
@@ -246,9 +228,20 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       }
       const bool any_fail = __any(!ok);
       const bool any_nf = __any(nonfinite);
-      wave_argmax(cv, ci);
+      // argmax over the wave carrying the signed value along
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const T ov = __shfl_xor(cv, off, 64);
+        const int oi = __shfl_xor(ci, off, 64);
+        const T opv = __shfl_xor(cpv, off, 64);
+        const bool take = (ov > cv) || (ov == cv && oi < ci);
+        cv = take ? ov : cv;
+        ci = take ? oi : ci;
+        cpv = take ? opv : cpv;
+      }
       if (lane == 0) {
         sh_gw = ci;
+        sh_pv = cpv;
         sh_code = 0;
         if (any_fail) {
           sh_code = 1;
@@ -268,35 +261,33 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       break;
     }
     const int gw = sh_gw;
+    const T pv = sh_pv;
+    const bool winner = (g == gw);
 
-    // ---- (4) the pivot: value, row index and row of the winner -------------
-    bool ok = true;
-    T pv;
-    ok = wait_value(&a.xval[((size_t)par * G + gw) * W], tag, pv, a.xflag, a.epoch);
-    int64_t prow = -1;
-    if (ok) ok = wait_index(&a.xidx[par * G + gw], tag, prow, a.xflag, a.epoch);
+    // ---- (4) multipliers, outputs, and the pivot row's words ---------------
+    // the row words are requested first; the divisions overlap their latency
     T uj = T(0);
-    if (ok && tid > t && tid < k)
+    bool ok = true;
+    if (!winner && tid > t && tid < k)
       ok = wait_value(a.xrow + (((size_t)par * G + gw) * a.kpad + tid) * W, tag, uj, a.xflag,
                       a.epoch);
-    if (!ok) sh_abort = 1;
-    if (ok) {
-      // multipliers (one per row, coalesced L writes); the pivot row gets 1
-      for (int q = tid; q < R; q += nt) {
-        const int64_t row = row0 + q;
-        const bool live = alive[q] && row != prow;
-        const T mq = live ? colbuf[q] / pv : T(0);
-        mult[q] = mq;
-        if (row < a.n) a.Lf[row + (int64_t)t * a.ldl] = live ? mq : (row == prow ? T(1) : T(0));
-      }
-      if (g == 0) {
-        if (tid == 0) {
-          a.J[t] = prow;
-          if (a.diag) a.diag[t] = fabs(pv);
-        }
-        if (tid < k) a.Uf[t + (int64_t)tid * a.ldu] = (tid > t) ? uj : (tid == t ? pv : T(0));
-      }
+    if (winner) uj = myv;
+    for (int q = tid; q < R; q += nt) {
+      const int64_t row = row0 + q;
+      const bool is_piv = winner && q == bq;
+      const bool live = alive[q] && !is_piv;
+      const T mq = live ? colbuf[q] / pv : T(0);
+      mult[q] = mq;
+      if (row < a.n) a.Lf[row + (int64_t)t * a.ldl] = live ? mq : (is_piv ? T(1) : T(0));
     }
+    if (winner) {
+      if (tid == 0) {
+        a.J[t] = row0 + bq;
+        if (a.diag) a.diag[t] = fabs(pv);
+      }
+      if (tid < k) a.Uf[t + (int64_t)tid * a.ldu] = (tid > t) ? myv : (tid == t ? pv : T(0));
+    }
+    if (!ok) sh_abort = 1;
     __syncthreads();
     if (sh_abort) {
       final_status = RPID_ERR_TIMEOUT;
@@ -304,6 +295,7 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     }
 
     // ---- (5) Schur update of this workgroup's rows, columns t+1..k-1 -------
+    if (winner && tid == 0) alive[bq] = 0;
     if (tid > t && tid < k) {
 #pragma unroll
       for (int q = 0; q < R; ++q) s[q] = fma(-mult[q], uj, s[q]);
@@ -312,7 +304,6 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
         for (int q = 0; q < R; ++q) colbuf[q] = s[q];
       }
     }
-    if (g == gw && tid == 0) alive[prow - row0] = 0;
     __syncthreads();
   }
   if (g == 0 && tid == 0) *a.status = final_status;
@@ -410,7 +401,6 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   constexpr int W = Words<T>::W;
   Carve cv;
   const size_t o_val = cv.take<uint64_t>((size_t)2 * G * W);
-  const size_t o_idx = cv.take<uint64_t>((size_t)2 * G);
   const size_t o_row = cv.take<uint64_t>((size_t)2 * G * kpad * W);
   const size_t o_flag = cv.take<uint64_t>(1);
   bool fresh = false;
@@ -446,7 +436,6 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   a.ldu = ldu;
   a.diag = diag;
   a.xval = reinterpret_cast<uint64_t*>(ucb + o_val);
-  a.xidx = reinterpret_cast<uint64_t*>(ucb + o_idx);
   a.xrow = reinterpret_cast<uint64_t*>(ucb + o_row);
   a.xflag = reinterpret_cast<uint64_t*>(ucb + o_flag);
   a.epoch = ctx->lupp_epoch;
