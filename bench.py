@@ -17,10 +17,18 @@ Prints one JSON line.  `value` is decompositions per second of the main
 mode (default bf16) with the inputs already in HBM.  `roofline` describes
 the kernel that takes the most time per step; `cpu_baseline` times the FP64
 numpy oracle on the host cores on one decomposition of the same workload.
+
+Before the timed region the script runs one plain device-to-device copy of
+CALIB_MIB MiB (a torch copy kernel that reads and writes exactly that many
+bytes); hardware byte counters taken over this same command are scaled by
+what they read for that copy.  `roofline.traffic` is filled from the
+counter summary committed under profiles/ only while the LUPP source file
+still has the hash recorded there, else it is null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +42,9 @@ K = 256
 L = 272
 PEAK_HBM = 8.0e12  # B/s, MI355X HBM3E
 PEAK_MFMA = {"bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}  # dense FLOP/s
+CALIB_MIB = 512
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lupp_poly8192_traffic.json")
+LUPP_SOURCE = os.path.join(ROOT, "paper_2104_05877_amd", "csrc", "lupp.hip")
 
 
 def parse():
@@ -45,6 +56,10 @@ def parse():
     ap.add_argument("--other-steps", type=int, default=8, help="timed steps of the other two modes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--only-main", action="store_true", help="time the main mode only")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: turn two rocprofv3 --pmc csv folders (FETCH_SIZE, "
+                         "WRITE_SIZE) of a --only-main run into the recorded LUPP traffic")
     return ap.parse_args()
 
 
@@ -74,6 +89,7 @@ def run_mode(torch, R, ctx, A, Om, steps, warmup):
     refine = 0 if A.dtype == torch.float64 else 1
     stream = ctx.stream
     names = ["sketch", "select_columns", "id_coeffs", "cur", "residual_id", "residual_cur"]
+    decomp = names[:4]  # sketch .. CUR; the residuals are reported on top
 
     def step(ev):
         ev[0].record(stream)
@@ -104,12 +120,90 @@ def run_mode(torch, R, ctx, A, Om, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     per = {n: 0.0 for n in names}
+    step_ms, decomp_ms = [], []
     for ev in evs:
         for j, n in enumerate(names):
             per[n] += ev[j].elapsed_time(ev[j + 1]) / steps  # ms
+        step_ms.append(ev[0].elapsed_time(ev[6]))
+        decomp_ms.append(ev[0].elapsed_time(ev[4]))
     rid, rcur, st_i, J, I = out
+    import numpy as np
+
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, per_call_ms=per, rid=rid, rcur=rcur,
-                status_cur=st_i, J=J.cpu().numpy(), I=I.cpu().numpy())
+                status_cur=st_i, J=J.cpu().numpy(), I=I.cpu().numpy(),
+                step_ms_p10_p50_p90=[float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
+                decomp_ms_p10_p50_p90=[float(np.percentile(decomp_ms, q)) for q in (10, 50, 90)])
+
+
+def calibration_copy(torch):
+    """One elementwise kernel that reads CALIB_MIB MiB and writes CALIB_MIB MiB
+    (a negating copy: a plain same-dtype copy would go to the DMA engines),
+    outside any timed region."""
+    n = CALIB_MIB * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def _counter_rows(folder):
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    per = {}
+    for fn in files:
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                key = (fn, r["Dispatch_Id"])
+                e = per.setdefault(key, {"kernel": r["Kernel_Name"], "value": 0.0})
+                e["value"] += float(r["Counter_Value"])
+    return list(per.values())
+
+
+def summarize_counters(fetch_dir, write_dir):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the LUPP launches of a
+    --only-main bf16 run, scaled by what the same counters read for the
+    calibration copy (CALIB_MIB MiB read, CALIB_MIB MiB written)."""
+    out = {}
+    for name, folder in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _counter_rows(folder)
+        calib = [r["value"] for r in rows if "neg" in r["kernel"].lower()]
+        lupp = [r["value"] for r in rows if "lupp_panel_kernel" in r["kernel"]]
+        if not calib or not lupp:
+            raise SystemExit(f"{name}: calibration copy or LUPP dispatches missing")
+        kib_expected = CALIB_MIB * 1024.0
+        factor = kib_expected / max(calib)
+        out[name] = {"calib_kib": max(calib), "factor": factor,
+                     "lupp_kib_mean": sum(lupp) / len(lupp), "lupp_launches": len(lupp),
+                     "lupp_bytes_per_launch": sum(lupp) / len(lupp) * 1024.0 * factor}
+    with open(LUPP_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    rec = {"kernel": "lupp_panel_kernel<float> on 8192 x 256 panels (bf16 mode)", "mode": "bf16",
+           "source_sha256": sha, "counters": out,
+           "hbm_bytes_per_launch": out["fetch"]["lupp_bytes_per_launch"]
+           + out["write"]["lupp_bytes_per_launch"]}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def recorded_traffic():
+    """Counter-measured HBM bytes per LUPP launch, if recorded for this source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(LUPP_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec
 
 
 def cpu_baseline(torch, A, Om):
@@ -132,6 +226,9 @@ def cpu_baseline(torch, A, Om):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -145,9 +242,12 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     log("generating poly8192 inputs on the GPU")
     data = make_inputs(torch, args.seed)
+    calibration_copy(torch)
     ctx = R.Context(0)
     results = {}
     order = [args.mode] + [m for m in ("bf16", "f32", "f64") if m != args.mode]
+    if args.only_main:
+        order = [args.mode]
     for mode in order:
         A, Om = data[mode]
         steps = args.steps if mode == args.mode else args.other_steps
@@ -170,9 +270,14 @@ def main():
     sketch_mfma = sketch_flops / t_sk / PEAK_MFMA[args.mode]
     if t_lu >= t_sk:
         ach = lupp_bytes / t_lu
+        rec = recorded_traffic()
+        traffic = None
+        if rec is not None and rec.get("mode") == args.mode:
+            traffic = rec["hbm_bytes_per_launch"]
         roof = {"kernel": "lupp_panel_kernel (column LUPP of X^T, 8192 x 256)", "bound": "hbm",
                 "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": ach / PEAK_HBM, "traffic": None, "avg_ms": per["select_columns"]}
+                "frac": ach / PEAK_HBM, "traffic": traffic, "algorithmic_bytes": lupp_bytes,
+                "avg_ms": per["select_columns"], "us_per_pivot": per["select_columns"] * 1e3 / K}
     else:
         if args.mode == "bf16":
             ach = sketch_bytes / t_sk
@@ -203,9 +308,13 @@ def main():
                    "step": "sketch + LUPP(X^T) + Z + CUR(LUPP(C), U) + ID/CUR residuals"},
         "sketch_mfma_util": sketch_mfma,
         "modes": {m: {"decomps_per_s": 1e3 / r["ms_per_step"], "ms_per_step": r["ms_per_step"],
+                      "step_ms_p10_p50_p90": r["step_ms_p10_p50_p90"],
                       "per_call_ms": r["per_call_ms"], "residual_id": r["rid"],
                       "residual_cur": r["rcur"]} for m, r in results.items()},
-        "speedup_bf16_vs_f64": results["f64"]["ms_per_step"] / results["bf16"]["ms_per_step"],
+        "speedup_bf16_vs_f64": (results["f64"]["ms_per_step"] / results["bf16"]["ms_per_step"]
+                                if "f64" in results and "bf16" in results else None),
+        "decomp_only": {m: {"decomps_per_s": 1e3 / r["decomp_ms_p10_p50_p90"][1],
+                            "ms_p10_p50_p90": r["decomp_ms_p10_p50_p90"]} for m, r in results.items()},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

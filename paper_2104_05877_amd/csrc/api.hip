@@ -124,9 +124,15 @@ static int chol_qr_pass(rpid_ctx ctx, int64_t m, int64_t n, int64_t k, const dou
   const int64_t kk = k * k;
   RPID_CHECK(dgemm(ctx, true, false, k, k, m, 1.0, C, m, C, m, 0.0, F, k, ws_tmp));
   RPID_CHECK(dgemm(ctx, true, false, k, k, n, 1.0, Rt, n, Rt, n, 0.0, F + kk, k, ws_tmp));
-  RPID_CHECK(cholesky_batched(ctx, 2, k, F, k, kk, status_dev));
-  RPID_CHECK(tri_inverse(ctx, k, F, k, false, false, Wi, k));
-  RPID_CHECK(tri_inverse(ctx, k, F + kk, k, false, false, Wi + kk, k));
+  if (sweep_supported(k)) {
+    // Cholesky factors and their inverses in one launch (the factors
+    // themselves are not needed)
+    RPID_CHECK(chol_inverse_batched(ctx, 2, k, F, k, kk, Wi, k, kk, status_dev, ws_tmp));
+  } else {
+    RPID_CHECK(cholesky_batched(ctx, 2, k, F, k, kk, status_dev));
+    RPID_CHECK(tri_inverse(ctx, k, F, k, false, false, Wi, k, ws_tmp));
+    RPID_CHECK(tri_inverse(ctx, k, F + kk, k, false, false, Wi + kk, k, ws_tmp));
+  }
   RPID_CHECK(dgemm(ctx, false, false, m, k, k, 1.0, C, m, Wi, k, 0.0, Cq, m, ws_tmp));
   RPID_CHECK(dgemm(ctx, false, false, n, k, k, 1.0, Rt, n, Wi + kk, k, 0.0, Rq, n, ws_tmp));
   return RPID_OK;
@@ -191,13 +197,11 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   double* Rt2 = ws_ptr<double>(ctx, o_Rt2);
   double* Wi = ws_ptr<double>(ctx, o_Wi);
   // pass 1: C, R^T -> C2, Rt2 (factors R1c, R1r in F[0..2), inverses in Wi[0..2))
+  // (a breakdown in pass 1 leaves garbage, never a fault, in what follows; the
+  // four statuses are checked once at the end)
   RPID_CHECK(chol_qr_pass(ctx, m, n, k, C64, Rt, C2, Rt2, F, Wi, status_dev, o_tmp));
-  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 2 * sizeof(int64_t),
-                                hipMemcpyDeviceToHost, ctx->stream));
-  RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
-  if (ctx->host_status[0] != 0 || ctx->host_status[1] != 0) return RPID_ERR_BREAKDOWN;
   // pass 2: C2, Rt2 -> Q_C (into C64), Q_R (into Rt) (factors R2c, R2r, inverses)
-  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C2, Rt2, C64, Rt, F + 2 * kk, Wi + 2 * kk, status_dev,
+  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C2, Rt2, C64, Rt, F + 2 * kk, Wi + 2 * kk, status_dev + 2,
                           o_tmp));
   // W = Q_C^T A (k x n), in the arithmetic of A's storage
   double* W = ws_ptr<double>(ctx, o_W);
@@ -229,6 +233,11 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi + kk, k, Wi + 3 * kk, k, 0.0, Tr, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Tc, k, M, k, 0.0, Y, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, true, k, k, k, 1.0, Y, k, Tr, k, 0.0, U, ldu, o_tmp));
+  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 4 * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, ctx->stream));
+  RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  for (int b = 0; b < 4; ++b)
+    if (ctx->host_status[b] != 0) return RPID_ERR_BREAKDOWN;
   return RPID_OK;
 }
 
@@ -504,7 +513,7 @@ int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64
     RPID_CHECK(gather_rows<double, double>(ctx, k, k, (const double*)Lf, ldl, n, J, LJ, k));
   else
     RPID_CHECK(gather_rows<float, double>(ctx, k, k, (const float*)Lf, ldl, n, J, LJ, k));
-  RPID_CHECK(tri_inverse(ctx, k, LJ, k, true, true, Winv, k));
+  RPID_CHECK(tri_inverse(ctx, k, LJ, k, true, true, Winv, k, o_tmp));
   // Z = W^T Lf^T: column j is L_J^{-T} Lf(j, :)^T, i.e. solves L_J^T z = Lf(j, :)^T
   const double* L64 = (const double*)Lf;
   int64_t ldl64 = ldl;
@@ -530,7 +539,7 @@ int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64
       RPID_CHECK(gather_columns<float, double>(ctx, k, k, (const float*)X, ldx, n, J, X1, k));
     }
     // X_1 = (L_J U')^T, so X_1^{-1} = (W_U W)^T with W_U = U'^{-1}
-    RPID_CHECK(tri_inverse(ctx, k, U64, k, false, false, WU, k));
+    RPID_CHECK(tri_inverse(ctx, k, U64, k, false, false, WU, k, o_tmp));
     RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, WU, k, Winv, k, 0.0, Pm, k, o_tmp));
     for (int it = 0; it < refine_steps; ++it) {
       // res = X_k - X_1 Z (FP64, X promoted); Z += X_1^{-1} res

@@ -134,7 +134,22 @@ int tri_solve(rpid_ctx ctx, int64_t k, int64_t nrhs, const double* T, int64_t ld
 
 // W = T^{-1} for a k x k triangular T (k <= 512), lower or upper, unit or not.
 int tri_inverse(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, bool lower, bool unit,
-                double* W, int64_t ldw);
+                double* W, int64_t ldw, size_t ws_tmp);
+
+// Register-resident triangular kernels (sweep.hip), k <= 288; the scratch
+// region at ws_tmp must hold sweep_scratch_bytes(k).
+bool sweep_supported(int64_t k);
+size_t sweep_scratch_bytes(int64_t k);
+// For `batch` (1 or 2) SPD k x k matrices G_b (stride apart, lower part
+// read): Cholesky G = R^T R and Winv_b = R^{-1} (upper, full matrix written).
+// status[b] = 0, or j+1 for a non-positive / non-finite pivot at column j
+// (the outputs are then undefined).
+int chol_inverse_batched(rpid_ctx ctx, int batch, int64_t k, const double* G, int64_t ldg,
+                         int64_t stride, double* Winv, int64_t ldw, int64_t wstride,
+                         int64_t* status_dev, size_t ws_tmp);
+// W = T^{-1} (full matrix written) for a lower or upper triangular k x k T.
+int tri_inverse_sweep(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, bool lower,
+                      bool unit, double* W, int64_t ldw, size_t ws_tmp);
 
 // Cholesky G = R^T R of `batch` SPD k x k matrices (in place, upper R; the
 // strict lower part is zeroed), one workgroup per matrix.  status[b] = 0 or

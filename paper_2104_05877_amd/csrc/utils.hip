@@ -666,8 +666,9 @@ int tri_solve(rpid_ctx ctx, int64_t k, int64_t nrhs, const double* T, int64_t ld
 }
 
 int tri_inverse(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, bool lower, bool unit,
-                double* W, int64_t ldw) {
+                double* W, int64_t ldw, size_t ws_tmp) {
   if (k < 1) return RPID_OK;
+  if (sweep_supported(k)) return tri_inverse_sweep(ctx, k, T, ldt, lower, unit, W, ldw, ws_tmp);
   const unsigned blocks = (unsigned)((k + 3) / 4);
   if (k <= 256)
     hipLaunchKernelGGL((tri_inverse_kernel<4, 8>), dim3(blocks), dim3(256), 0, ctx->stream, (int)k, T,

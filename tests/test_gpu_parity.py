@@ -197,6 +197,35 @@ def test_exp1000x800_f64_end_to_end(R, ctx):
     assert abs(rcur - ro["cur"]) <= 1e-9 * ro["cur"]
 
 
+@pytest.mark.parametrize("m,n,k,l,seed", [(2048, 1800, 256, 272, 5), (1500, 1700, 200, 200, 6),
+                                          (1300, 1100, 170, 180, 7)])
+def test_large_k_f64_end_to_end(R, ctx, m, n, k, l, seed):
+    """k above what one workgroup holds in registers (the triangular factors
+    are split into 2 x 2 blocks), k not a multiple of 32: J and I bit-exact,
+    Z within its conditioning, U through the CUR residual (1e-9 relative)."""
+    say("large-k f64", m, n, k, l)
+    A, Om = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 1.0), seed)
+    o = O.decompose(A, Om, k, gaps=True)
+    assert o["gap_J"].min() > 1e-9 and o["gap_I"].min() > 1e-9
+    Ad, Od = dev(A), dev(Om)
+    g = R.decompose(ctx, Ad, Od, k, want_eta=True)
+    assert g["status"] == 0 and g["status_I"] == 0
+    assert np.array_equal(host(g["J"]).astype(np.int64), o["J"])
+    assert np.array_equal(host(g["I"]).astype(np.int64), o["I"])
+    Zg = host(g["Z"])
+    kappa = np.linalg.cond(o["X"][:k][:, o["J"]])
+    np.testing.assert_allclose(Zg, o["Z"], rtol=0, atol=1e-13 * kappa * max(1.0, np.abs(o["Z"]).max()))
+    assert abs(g["eta"] - o["eta"]) <= 1e-6 * o["eta"]
+    Ug = host(g["U"])
+    np.testing.assert_allclose(Ug, o["U"], rtol=1e-6, atol=1e-6 * np.abs(o["U"]).max())
+    ro = O.residuals(A, o["J"], Z=o["Z"], I=o["I"], U=o["U"], only=("id", "cur"))
+    rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, g["J"], Z=g["Z"])
+    rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, k, g["J"], I=g["I"], U=g["U"])
+    say("residuals gpu", rid, rcur, "oracle", ro["id"], ro["cur"])
+    assert abs(rid - ro["id"]) <= 1e-9 * ro["id"]
+    assert abs(rcur - ro["cur"]) <= 1e-9 * ro["cur"]
+
+
 @pytest.mark.parametrize("m,n,k,seed", [(300, 257, 16, 1), (1500, 900, 100, 2)])
 def test_exact_recovery_gpu(R, ctx, m, n, k, seed):
     """rank(A) = k, l = k: the GPU's ID and CUR residuals are at round-off."""
