@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--only-main", action="store_true", help="time the main mode only")
+    ap.add_argument("--input-cache", default=None,
+                    help="folder: load the FP32 workload from it if stored there, else "
+                         "generate it and store it (lets profiled runs skip the QR-based "
+                         "generation)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU work: turn two rocprofv3 --pmc csv folders (FETCH_SIZE, "
                          "WRITE_SIZE) of a --only-main run into the recorded LUPP traffic")
@@ -67,14 +71,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def make_inputs(torch, seed):
+def make_inputs(torch, seed, cache=None):
     from paper_2104_05877_amd import inputs
 
-    s = inputs.poly_spectrum(N, 2.0)
-    a64 = inputs.torch_spectral(M, N, s, seed, "cuda")
-    a32 = a64.T.contiguous().float().T  # FP32 storage of the workload
-    del a64
-    om32 = inputs.torch_gaussian(L, M, seed + 7, "cuda").T.contiguous().float().T
+    path = os.path.join(cache, f"poly8192_seed{seed}.pt") if cache else None
+    if path and os.path.exists(path):
+        d = torch.load(path, weights_only=True)
+        # stored as the contiguous transposes (n x m and m x l)
+        a32 = d["a_t"].cuda().T
+        om32 = d["om_t"].cuda().T
+    else:
+        s = inputs.poly_spectrum(N, 2.0)
+        a64 = inputs.torch_spectral(M, N, s, seed, "cuda")
+        a32 = a64.T.contiguous().float().T  # FP32 storage of the workload
+        del a64
+        om32 = inputs.torch_gaussian(L, M, seed + 7, "cuda").T.contiguous().float().T
+        if path:
+            os.makedirs(cache, exist_ok=True)
+            torch.save({"a_t": a32.T.cpu(), "om_t": om32.T.cpu()}, path)
     out = {
         "f32": (a32, om32),
         "f64": (a32.T.contiguous().double().T, om32.T.contiguous().double().T),
@@ -241,7 +255,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     log("generating poly8192 inputs on the GPU")
-    data = make_inputs(torch, args.seed)
+    data = make_inputs(torch, args.seed, args.input_cache)
     calibration_copy(torch)
     ctx = R.Context(0)
     results = {}
