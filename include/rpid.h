@@ -199,6 +199,16 @@ int rpid_mlp_backward(rpid_ctx ctx, const float* W, const float* feats, const fl
                       const float* dy, int64_t B, float* dW);
 int rpid_mlp_adam(rpid_ctx ctx, float* W, const float* dW, float* m1, float* m2, float lr,
                   int64_t t);
+/*
+ * Training loss of the rank network: pinball (quantile) loss at level tau in
+ * (0, 1) on targets log2 k*, r = target - yhat,
+ *   loss = mean_b (tau max(r_b, 0) + (1 - tau) max(-r_b, 0)),
+ * so that predicting a rank below k* (which costs a fallback) weighs tau /
+ * (1 - tau) times more than predicting above it.  dy[B] (device) receives
+ * d loss / d yhat (subgradient 0 at r = 0); *loss is one device float.
+ */
+int rpid_mlp_loss(rpid_ctx ctx, const float* yhat, const float* target, int64_t B, float tau,
+                  float* dy, float* loss);
 
 #ifdef __cplusplus
 }

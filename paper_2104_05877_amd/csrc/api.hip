@@ -24,6 +24,7 @@ int mlp_backward(rpid_ctx, const float*, const float*, const float*, const float
                  float*, size_t);
 int mlp_adam(rpid_ctx, float*, const float*, float*, float*, float, int64_t);
 int mlp_features(rpid_ctx, const void*, bool, int64_t, int64_t, float*);
+int mlp_pinball(rpid_ctx, const float*, const float*, int64_t, float, float*, float*);
 size_t mlp_backward_workspace(int64_t B);
 int sketch_fp8(rpid_ctx, const float*, int64_t, int64_t, int64_t, const float*, int64_t, int64_t,
                float*, int64_t, size_t);
@@ -667,6 +668,19 @@ int rpid_mlp_adam(rpid_ctx ctx, float* W, const float* dW, float* m1, float* m2,
   if (t < 1) return -7;
   RPID_HIP_CHECK(hipSetDevice(ctx->device));
   return mlp_adam(ctx, W, dW, m1, m2, lr, t);
+}
+
+int rpid_mlp_loss(rpid_ctx ctx, const float* yhat, const float* target, int64_t B, float tau,
+                  float* dy, float* loss) {
+  if (!ctx) return -1;
+  if (!yhat) return -2;
+  if (!target) return -3;
+  if (B < 1) return -4;
+  if (!(tau > 0.0f && tau < 1.0f)) return -5;
+  if (!dy) return -6;
+  if (!loss) return -7;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  return mlp_pinball(ctx, yhat, target, B, tau, dy, loss);
 }
 
 }  // extern "C"

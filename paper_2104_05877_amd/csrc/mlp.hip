@@ -167,6 +167,30 @@ __global__ void adam_kernel(float* W, const float* g, float* m1, float* m2, floa
   }
 }
 
+// Pinball (quantile) loss on the network output: r = target - yhat,
+// loss = mean(tau max(r, 0) + (1 - tau) max(-r, 0)); dy = d loss / d yhat.
+// One workgroup; the mean is summed in FP64 in a fixed order.
+__global__ __launch_bounds__(256) void pinball_kernel(const float* yhat, const float* target,
+                                                      int64_t B, float tau, float* dy,
+                                                      float* loss) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  const float inv = 1.0f / (float)B;
+  for (int64_t b = threadIdx.x; b < B; b += 256) {
+    const float r = target[b] - yhat[b];
+    const float l = (r > 0.0f) ? tau * r : (tau - 1.0f) * r;
+    dy[b] = ((r > 0.0f) ? -tau : (r < 0.0f ? 1.0f - tau : 0.0f)) * inv;
+    acc += (double)l;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (float)(part[0] / (double)B);
+}
+
 template <typename T>
 __global__ void features_kernel(const T* d, int64_t L, int64_t k_eff, float* f) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L;
@@ -211,6 +235,14 @@ int mlp_adam(rpid_ctx ctx, float* W, const float* dW, float* m1, float* m2, floa
   const float c2 = 1.0f - powf(0.999f, (float)t);
   hipLaunchKernelGGL(adam_kernel, dim3(324), dim3(256), 0, ctx->stream, W, dW, m1, m2, lr, c1,
                      c2);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+
+int mlp_pinball(rpid_ctx ctx, const float* yhat, const float* target, int64_t B, float tau,
+                float* dy, float* loss) {
+  hipLaunchKernelGGL(pinball_kernel, dim3(1), dim3(256), 0, ctx->stream, yhat, target, B, tau, dy,
+                     loss);
   RPID_HIP_CHECK(hipGetLastError());
   return RPID_OK;
 }

@@ -60,6 +60,7 @@ _SIGS = {
     "rpid_mlp_forward": (_i, [_P, _P, _P, _I, _P, _P]),
     "rpid_mlp_backward": (_i, [_P, _P, _P, _P, _P, _I, _P]),
     "rpid_mlp_adam": (_i, [_P, _P, _P, _P, _P, ctypes.c_float, _I]),
+    "rpid_mlp_loss": (_i, [_P, _P, _P, _I, ctypes.c_float, _P, _P]),
 }
 
 
@@ -269,6 +270,17 @@ def rpid_mlp_backward(ctx, W, feats, act, dy):
 def rpid_mlp_adam(ctx, W, dW, m1, m2, lr, t):
     _check("rpid_mlp_adam", lib().rpid_mlp_adam(
         ctx.handle, W.data_ptr(), dW.data_ptr(), m1.data_ptr(), m2.data_ptr(), float(lr), int(t)))
+
+
+def rpid_mlp_loss(ctx, yhat, target, tau):
+    """Pinball loss (device float tensor of one element) and its gradient dy."""
+    B = yhat.shape[0]
+    dy = torch.empty(B, dtype=torch.float32, device=yhat.device)
+    loss = torch.empty(1, dtype=torch.float32, device=yhat.device)
+    _check("rpid_mlp_loss", lib().rpid_mlp_loss(
+        ctx.handle, yhat.contiguous().data_ptr(), target.contiguous().data_ptr(), B, float(tau),
+        dy.data_ptr(), loss.data_ptr()))
+    return loss, dy
 
 
 def decompose(ctx, A, Omega, k, refine_steps=None, want_eta=False, want_cur=True):
