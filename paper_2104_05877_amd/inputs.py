@@ -185,3 +185,40 @@ def torch_nonneg_lowrank(m, n, r, noise, seed, device):
     at = (f @ g).T.contiguous()
     at += noise * torch.rand((n, m), generator=gen, dtype=torch.float32, device=device)
     return at.T
+
+
+# ---------------------------------------------------------------------------
+# learned-rank stream: matrices drawn per index from a seed-chosen mix of
+# exponential and polynomial spectral decays
+# ---------------------------------------------------------------------------
+def stream_spec(index, seed=0, m_range=(2048, 8192), n_range=(2048, 8192),
+                rate_range=(1e-3, 1e-1), power_range=(0.5, 3.0), floor=1e-12):
+    """(m, n, spectrum, family) of matrix `index` of a stream: m, n uniform
+    integers in their ranges; with probability 1/2 s_i = exp(-rate (i-1)) with
+    rate log-uniform, else s_i = i^-power with power uniform; truncated where
+    s_i / s_1 < floor."""
+    rng = rng_for(40 + seed, index, STREAM_NOISE)
+    m = int(rng.integers(m_range[0], m_range[1] + 1))
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    r = min(m, n)
+    i = np.arange(r, dtype=np.float64)
+    if rng.random() < 0.5:
+        rate = float(np.exp(rng.uniform(np.log(rate_range[0]), np.log(rate_range[1]))))
+        spec, fam = np.exp(-rate * i), ("exp", rate)
+    else:
+        power = float(rng.uniform(power_range[0], power_range[1]))
+        spec, fam = (i + 1.0) ** (-power), ("poly", power)
+    spec = spec[spec >= floor * spec[0]]
+    return m, n, spec, fam
+
+
+def torch_stream_case(index, lmax, device, seed=0, **ranges):
+    """Matrix `index` of the stream on the GPU: (A64, Omega64 (lmax x m),
+    A_bf16, Omega_bf16, family), column-major."""
+    torch = _torch()
+    m, n, spec, fam = stream_spec(index, seed, **ranges)
+    a64 = torch_spectral(m, n, spec, 100003 * (seed + 1) + 7 * index, device)
+    om64 = torch_gaussian(lmax, m, 200003 * (seed + 1) + 11 * index, device)
+    a16 = a64.T.contiguous().bfloat16().T
+    om16 = om64.T.contiguous().bfloat16().T
+    return a64, om64, a16, om16, fam

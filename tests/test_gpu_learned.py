@@ -1,0 +1,205 @@
+"""GPU tests of the learned-rank form: the library's feature, MLP, loss and
+Adam kernels against the FP64 oracle, labels from the plain FP64 path
+against the oracle's scan, and what the trained network gains over rank
+doubling on held-out matrices."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle.mlp_oracle as MO  # noqa: E402
+from paper_2104_05877_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# a small stream whose labels mostly fall inside the sketch (lmax = 64)
+SMALL = dict(m_range=(256, 480), n_range=(256, 480), rate_range=(0.2, 2.0), power_range=(3.0, 7.0))
+TOL = 1e-4
+LMAX = 64
+
+
+def say(*a):
+    print("[learned]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2104_05877_amd import rpid
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return rpid
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2104_05877_amd import learned
+
+    return learned
+
+
+def _weights(seed, scale=0.05):
+    rng = np.random.default_rng([seed, 5])
+    return (rng.standard_normal(MO.NPARAM) * scale).astype(np.float32)
+
+
+def test_features_parity(R, ctx):
+    say("features")
+    rng = np.random.default_rng(3)
+    for dt, L_, k_eff in ((torch.float32, 512, 300), (torch.float64, 512, 512), (torch.float32, 100, 37)):
+        d = np.sort(np.abs(rng.standard_normal(L_)) * 10.0 ** rng.uniform(-25, 0, L_))[::-1].copy()
+        d[k_eff:] = 0.0
+        dd = torch.tensor(d, dtype=dt, device="cuda")
+        f = R.rpid_mlp_features(ctx, dd, 512 if L_ == 512 else L_, k_eff).cpu().numpy()
+        fo = MO.features(dd.double().cpu().numpy(), f.shape[0], k_eff)
+        np.testing.assert_allclose(f, fo, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("B", [1, 16, 37, 300])
+def test_mlp_forward_backward_parity(R, ctx, B):
+    """FP32 kernels against the FP64 oracle on the same FP32 values."""
+    say("mlp fwd/bwd B =", B)
+    # inputs whose hidden pre-activations all keep a margin from zero, so that
+    # FP32 and FP64 agree on every ReLU mask (decided on the oracle's values)
+    for seed in range(B, B + 200):
+        rng = np.random.default_rng(seed)
+        W = _weights(seed)
+        X = rng.uniform(-20.0, 0.0, (B, MO.IN)).astype(np.float32)
+        yo, cache = MO.forward(W.astype(np.float64), X.astype(np.float64))
+        if min(np.abs(cache[0]).min(), np.abs(cache[2]).min()) > 5e-5:
+            break
+    else:
+        pytest.fail("no input set with a ReLU margin")
+    Wd = torch.tensor(W, device="cuda")
+    Xd = torch.tensor(X, device="cuda")
+    y, act = R.rpid_mlp_forward(ctx, Wd, Xd)
+    scale = np.abs(yo).max() + 1.0
+    np.testing.assert_allclose(y.cpu().numpy(), yo, rtol=0, atol=2e-5 * scale)
+    dy = rng.standard_normal(B).astype(np.float32)
+    dW = R.rpid_mlp_backward(ctx, Wd, Xd, act, torch.tensor(dy, device="cuda")).cpu().numpy()
+    go = MO.backward(W.astype(np.float64), X.astype(np.float64), cache, dy.astype(np.float64))
+    # block by block, relative to the block's norm
+    bounds = [MO.OFF_W1, MO.OFF_B1, MO.OFF_W2, MO.OFF_B2, MO.OFF_W3, MO.OFF_B3, MO.NPARAM]
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        err = np.linalg.norm(dW[lo:hi] - go[lo:hi])
+        ref = np.linalg.norm(go[lo:hi]) + 1e-6
+        assert err <= 1e-4 * ref, (lo, err, ref)
+
+
+def test_loss_and_adam_parity(R, ctx):
+    say("loss, adam")
+    rng = np.random.default_rng(9)
+    B = 203
+    y = rng.standard_normal(B).astype(np.float32)
+    t = rng.standard_normal(B).astype(np.float32)
+    t[:5] = y[:5]  # r = 0 exactly
+    loss, dy = R.rpid_mlp_loss(ctx, torch.tensor(y, device="cuda"), torch.tensor(t, device="cuda"), 0.9)
+    lo, dyo = MO.pinball(y.astype(np.float64), t.astype(np.float64), 0.9)
+    assert abs(float(loss) - lo) <= 1e-6 * abs(lo)
+    np.testing.assert_allclose(dy.cpu().numpy(), dyo, rtol=1e-6, atol=1e-9)
+    W = _weights(1)
+    g = rng.standard_normal(MO.NPARAM).astype(np.float32)
+    Wd, gd = torch.tensor(W, device="cuda"), torch.tensor(g, device="cuda")
+    m1, m2 = torch.zeros_like(Wd), torch.zeros_like(Wd)
+    Wo, m1o, m2o = W.astype(np.float64), np.zeros(MO.NPARAM), np.zeros(MO.NPARAM)
+    for step in range(1, 4):
+        R.rpid_mlp_adam(ctx, Wd, gd, m1, m2, 1e-3, step)
+        Wo, m1o, m2o = MO.adam(Wo, g.astype(np.float64), m1o, m2o, 1e-3, step)
+    np.testing.assert_allclose(Wd.cpu().numpy(), Wo, rtol=0, atol=2e-6)
+
+
+def test_training_loss_matches_oracle(R, ctx, L):
+    """Twenty Adam steps on a fixed batch: the GPU's loss trajectory follows
+    the FP64 oracle's training on the same data."""
+    say("training trajectory")
+    rng = np.random.default_rng(4)
+    B = 48
+    X = rng.uniform(-20.0, 0.0, (B, MO.IN)).astype(np.float32)
+    T = rng.uniform(1.0, 6.0, B).astype(np.float32)
+    net = L.RankNet(ctx, seed=3)
+    W0 = net.W.cpu().numpy().astype(np.float64)
+    Xd, Td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
+    g_loss = [float(net.step(Xd, Td, 0.9, 1e-3)) for _ in range(20)]
+    Wo, m1, m2 = W0, np.zeros(MO.NPARAM), np.zeros(MO.NPARAM)
+    o_loss = []
+    for step in range(1, 21):
+        y, cache = MO.forward(Wo, X.astype(np.float64))
+        lo, dy = MO.pinball(y, T.astype(np.float64), 0.9)
+        o_loss.append(lo)
+        Wo, m1, m2 = MO.adam(Wo, MO.backward(Wo, X.astype(np.float64), cache, dy), m1, m2, 1e-3, step)
+    say("gpu", g_loss[0], g_loss[-1], "oracle", o_loss[0], o_loss[-1])
+    np.testing.assert_allclose(g_loss, o_loss, rtol=2e-3, atol=1e-5)
+    assert g_loss[-1] < 0.5 * g_loss[0]
+
+
+def test_rank_labels_match_oracle(R, ctx, L):
+    """Plain FP64 path labels (bisection) against the oracle's scan of every
+    rank on the same matrices; where the residual crosses the tolerance more
+    than once, the GPU's label must still be a crossing."""
+    say("labels")
+    for idx in range(6):
+        m, n, spec, fam = inputs.stream_spec(idx, 0, **SMALL)
+        A64, Om64, _, _, _ = inputs.torch_stream_case(idx, LMAX, "cuda", 0, **SMALL)
+        k, evals = L.rank_label(ctx, A64, Om64, TOL, LMAX)
+        A = A64.cpu().numpy()
+        Om = Om64.cpu().numpy()
+        ko = MO.rank_label(A, Om, TOL, LMAX)
+        say(idx, m, n, fam, "gpu", k, "oracle", ko, "evals", evals)
+        if k == ko:
+            continue
+        assert k is not None and ko is not None
+        from oracle import rpid_oracle as O
+
+        X = O.sketch(A, Om[:LMAX])
+        J = O.lupp_colwise(X, LMAX)["J"]
+        assert MO.id_residual_at(A, X, J, k) <= TOL < MO.id_residual_at(A, X, J, k - 1)
+
+
+def _dataset(ctx, L, idx_range, l_feat):
+    feats, labels = [], []
+    for idx in idx_range:
+        A64, Om64, A16, Om16, _ = inputs.torch_stream_case(idx, LMAX, "cuda", 0, **SMALL)
+        k, _ = L.rank_label(ctx, A64, Om64, TOL, LMAX)
+        feats.append(L.profile_features(ctx, A16, Om16, l_feat))
+        labels.append(k)
+    return torch.stack(feats), labels
+
+
+def test_learned_rank_gain(R, ctx, L):
+    """Train on 160 matrices of the stream, judge on 48 held out: every
+    answer meets the tolerance (the plain path is the fallback), and the
+    network needs fewer FP64 attempts than rank doubling from 4."""
+    say("learned gain: building the stream")
+    ftr, ytr = _dataset(ctx, L, range(0, 160), LMAX)
+    targets = torch.tensor([L.target_of(k, LMAX) for k in ytr], dtype=torch.float32, device="cuda")
+    net = L.RankNet(ctx, seed=1)
+    hist = net.fit(ftr, targets, epochs=300, batch=32, lr=2e-3, tau=0.9, seed=2)
+    say("train loss", hist[0], "->", hist[-1])
+    assert hist[-1] < 0.3 * hist[0]
+    att_l, att_d, t_l, t_d, misses = [], [], [], [], 0
+    for idx in range(1000, 1048):
+        A64, Om64, A16, Om16, fam = inputs.torch_stream_case(idx, LMAX, "cuda", 0, **SMALL)
+        kd, ed, sd = L.solve_doubling(ctx, A64, Om64, TOL, 4, LMAX)
+        kl, el, sl, khat = L.solve_learned(ctx, net, A64, Om64, A16, Om16, TOL, LMAX, LMAX)
+        if kl is not None:
+            r = L.attempt(ctx, A64, Om64, kl)
+            assert r <= TOL, (idx, kl, r)
+            misses += int(khat < kl)
+        att_l.append(el)
+        att_d.append(ed)
+        t_l.append(sl)
+        t_d.append(sd)
+    say("attempts learned", np.mean(att_l), "doubling", np.mean(att_d),
+        "time learned", np.sum(t_l), "doubling", np.sum(t_d), "under-predictions", misses)
+    assert np.mean(att_l) < np.mean(att_d)
