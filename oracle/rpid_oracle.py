@@ -42,6 +42,9 @@ import scipy.linalg as sla
 
 __all__ = [
     "sketch",
+    "sketch_fp8",
+    "e4m3_round",
+    "fp8_scale_exp",
     "lupp_colwise",
     "lupp_rowwise",
     "id_coeffs",
@@ -68,6 +71,62 @@ def _f64(a):
 def sketch(A, Omega):
     """X = Omega A (l x n) in float64 (Alg. 2, step 2)."""
     return _f64(Omega) @ _f64(A)
+
+
+# --------------------------------------------------------------------------
+# FP8 form of Alg. 2 step 2 (precision form, not in the paper): OCP E4M3
+# operands with power-of-two scales, exact product of the quantised values
+# --------------------------------------------------------------------------
+E4M3_MAX = 448.0
+
+
+def e4m3_values():
+    """The 127 finite non-negative OCP E4M3 values in code order: exponent
+    field e (bias 7) and 3-bit mantissa f; e = 0 is subnormal (f 2^-9);
+    code 0x7F is NaN and there are no infinities."""
+    vals = []
+    for code in range(0x7F):
+        e, f = code >> 3, code & 7
+        vals.append(f * 2.0**-9 if e == 0 else (1.0 + f / 8.0) * 2.0 ** (e - 7))
+    return np.array(vals)
+
+
+def e4m3_round(x):
+    """Round to the nearest E4M3 value, ties to the even code (|x| <= 448)."""
+    x = _f64(x)
+    table = e4m3_values()
+    a = np.abs(x)
+    hi = np.clip(np.searchsorted(table, a, side="left"), 0, table.size - 1)
+    lo = np.clip(hi - 1, 0, table.size - 1)
+    dlo, dhi = a - table[lo], table[hi] - a
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0))
+    code = np.where(pick_hi, hi, lo)
+    code = np.where(a >= table[-1], table.size - 1, code)
+    return np.sign(x) * table[code]
+
+
+def fp8_scale_exp(mx):
+    """Largest integer e with mx * 2^e <= 448 (0 for mx == 0)."""
+    if not (mx > 0):
+        return 0
+    e = int(np.floor(np.log2(E4M3_MAX / mx)))
+    while np.ldexp(mx, e + 1) <= E4M3_MAX:
+        e += 1
+    while np.ldexp(mx, e) > E4M3_MAX:
+        e -= 1
+    return e
+
+
+def sketch_fp8(A, Omega):
+    """X = (Om_q A_q) 2^-(eo + ea_j) with A_q(:, j) = e4m3(A(:, j) 2^ea_j) and
+    Om_q = e4m3(Omega 2^eo), the exponents chosen per column of A and for
+    all of Omega so that the largest modulus lands on or below 448."""
+    A, Omega = _f64(A), _f64(Omega)
+    ea = np.array([fp8_scale_exp(np.abs(A[:, j]).max()) for j in range(A.shape[1])])
+    eo = fp8_scale_exp(np.abs(Omega).max())
+    Aq = e4m3_round(A * np.ldexp(1.0, ea)[None, :])
+    Oq = e4m3_round(Omega * np.ldexp(1.0, eo))
+    return (Oq @ Aq) * np.ldexp(1.0, -(eo + ea))[None, :]
 
 
 # --------------------------------------------------------------------------

@@ -427,7 +427,9 @@ int rpid_sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t 
   if (!X) return -9;
   if (ldx < l) return -10;
   RPID_HIP_CHECK(hipSetDevice(ctx->device));
-  RPID_CHECK(ensure_workspace(ctx, sketch_fp8_workspace(m, n, l)));
+  const int64_t mq = (m + 127) / 128 * 128;
+  RPID_CHECK(ensure_workspace(ctx, sketch_fp8_workspace(m, n, l) +
+                                       sketch_workspace_bytes(ctx, mq, n, l, 4)));
   return sketch_fp8(ctx, A, m, n, lda, Omega, l, ldo, X, ldx, 0);
 }
 

@@ -1,21 +1,194 @@
-// FP8 (OCP E4M3) form of the row sketch: placeholder until the FP8 MFMA
-// kernel lands; reports the combination as unsupported.
+// FP8 (OCP E4M3) form of the row sketch X = Omega A (Alg. 2, step 2).
+//
+//   ea[j] = largest e with max_i |A(i, j)| * 2^e <= 448 (0 for a zero column)
+//   eo    = largest e with max |Omega| * 2^e <= 448
+//   A_q(:, j) = e4m3(A(:, j) * 2^ea[j]),  Om_q = e4m3(Omega * 2^eo)
+//   X(:, j)   = (Om_q A_q)(:, j) * 2^-(eo + ea[j])
+//
+// e4m3 rounds to nearest, ties to the even code; the power-of-two scales keep
+// every scaled value within +-448, so nothing saturates, and undoing them in
+// X is exact.  The product runs on the FP8 MFMA (16 x 16 x 128, FP32
+// accumulation) through the common sketch kernel.  Non-finite entries give
+// NaN codes, hence a non-finite X that the LUPP reports.
 #include "rpid_internal.hpp"
 
 namespace rpid {
 
+namespace {
+
+constexpr float E4M3_MAX = 448.0f;
+
+// RNE conversion of |x| <= 448 (or NaN) to its E4M3 code.
+__device__ __forceinline__ uint32_t e4m3_code(float x) {
+  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fabsf(x);
+  if (!(a == a)) return 0x7Fu | sign;
+  uint32_t code;
+  if (a < 0.015625f) {
+    // below the smallest normal 2^-6: multiples of 2^-9 (code 8 is 2^-6 itself)
+    code = (uint32_t)__builtin_rintf(a * 512.0f);
+  } else {
+    uint32_t b = __float_as_uint(a);
+    b += 0x7FFFFu + ((b >> 20) & 1u);  // round the 23-bit mantissa to 3 bits, ties to even
+    code = (b >> 20) - ((127u - 7u) << 3);
+    if (code > 0x7Eu) code = 0x7Eu;
+  }
+  return code | sign;
+}
+
+// largest e with mx * 2^e <= 448 (mx > 0 finite); 0 otherwise
+__device__ __forceinline__ int scale_exp(float mx) {
+  if (!(mx > 0.0f) || !isfinite(mx)) return 0;
+  int e = 8 - ilogbf(mx);
+  while (ldexpf(mx, e) > E4M3_MAX) --e;
+  while (ldexpf(mx, e + 1) <= E4M3_MAX) ++e;
+  return e;
+}
+
+__device__ __forceinline__ float block_max(float v, float* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  float r = red[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = fmaxf(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// one workgroup per column: max |A(:, j)| -> ea[j], then the quantised column
+__global__ __launch_bounds__(256) void quantize_cols_kernel(const float* A, int64_t m, int64_t lda,
+                                                            uint8_t* Aq, int64_t ldq, int* ea) {
+  __shared__ float red[4];
+  const int64_t j = blockIdx.x;
+  const float* col = A + j * lda;
+  float mx = 0.0f;
+  bool nonfinite = false;
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    const float v = fabsf(col[i]);
+    nonfinite |= !isfinite(v);
+    mx = fmaxf(mx, v);
+  }
+  mx = block_max(mx, red);
+  const bool any_nf = __syncthreads_or(nonfinite);
+  const int e = any_nf ? 0 : scale_exp(mx);
+  if (threadIdx.x == 0) ea[j] = e;
+  uint8_t* q = Aq + j * ldq;
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    const float v = col[i];
+    q[i] = (uint8_t)e4m3_code(isfinite(v) ? ldexpf(v, e) : NAN);
+  }
+}
+
+// partial maxima of |Omega| (l x m), one per workgroup
+__global__ __launch_bounds__(256) void omega_max_kernel(const float* Om, int64_t l, int64_t m,
+                                                        int64_t ldo, float* part) {
+  __shared__ float red[4];
+  float mx = 0.0f;
+  const int64_t total = l * m;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const float v = fabsf(Om[(e % l) + (e / l) * ldo]);
+    mx = (v == v) ? fmaxf(mx, v) : INFINITY;
+  }
+  mx = block_max(mx, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+// eo from the partial maxima, then Pt_q = e4m3(Omega^T * 2^eo) (m x l, ldq)
+// through 32 x 32 LDS tiles; every workgroup reduces the partials itself
+__global__ __launch_bounds__(256) void quantize_omega_t_kernel(const float* Om, int64_t l, int64_t m,
+                                                               int64_t ldo, const float* part,
+                                                               int nparts, uint8_t* Ptq,
+                                                               int64_t ldq, int* eo_out) {
+  __shared__ float tile[32][33];
+  __shared__ int s_e;
+  if (threadIdx.x == 0) {
+    float mx = 0.0f;
+    for (int i = 0; i < nparts; ++i) mx = fmaxf(mx, part[i]);
+    s_e = scale_exp(mx);
+    if (blockIdx.x == 0 && blockIdx.y == 0) *eo_out = s_e;
+  }
+  __syncthreads();
+  const int e = s_e;
+  const int64_t r0 = (int64_t)blockIdx.y * 32, i0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t r = r0 + tx, i = i0 + yy;
+    tile[yy][tx] = (r < l && i < m) ? Om[r + i * ldo] : 0.0f;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t i = i0 + tx, r = r0 + yy;
+    if (r < l && i < m) {
+      const float v = tile[tx][yy];
+      Ptq[i + r * ldq] = (uint8_t)e4m3_code(isfinite(v) ? ldexpf(v, e) : NAN);
+    }
+  }
+}
+
+// X(:, j) *= 2^-(eo + ea[j])
+__global__ void unscale_kernel(float* X, int64_t l, int64_t n, int64_t ldx, const int* ea,
+                               const int* eo) {
+  const int64_t total = l * n;
+  const int e0 = *eo;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % l, j = e / l;
+    X[r + j * ldx] = ldexpf(X[r + j * ldx], -(e0 + ea[j]));
+  }
+}
+
+constexpr int OMAX_PARTS = 512;
+
+}  // namespace
+
 size_t sketch_fp8_workspace(int64_t m, int64_t n, int64_t l) {
-  (void)m;
-  (void)n;
-  (void)l;
-  return 256;
+  const int64_t mq = (m + 127) / 128 * 128;  // quantised rows padded to the MFMA depth
+  return (size_t)mq * n + (size_t)mq * l + (size_t)n * sizeof(int) + 64 +
+         OMAX_PARTS * sizeof(float) + 4096;
 }
 
 int sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* Om,
                int64_t l, int64_t ldo, float* X, int64_t ldx, size_t ws_off) {
-  (void)ctx; (void)A; (void)m; (void)n; (void)lda; (void)Om; (void)l; (void)ldo; (void)X;
-  (void)ldx; (void)ws_off;
-  return RPID_ERR_UNSUPPORTED;
+  // quantised copies padded with zero codes to a multiple of 128 rows, so the
+  // pipelined kernel (whole 128-deep stages, 16-byte aligned) always applies
+  const int64_t mq = (m + 127) / 128 * 128;
+  Carve cv;
+  cv.off = ws_off;
+  const size_t o_Aq = cv.take<uint8_t>((size_t)mq * n);
+  const size_t o_Pq = cv.take<uint8_t>((size_t)mq * l);
+  const size_t o_ea = cv.take<int>((size_t)n);
+  const size_t o_eo = cv.take<int>(16);
+  const size_t o_part = cv.take<float>(OMAX_PARTS);
+  const size_t o_gemm = cv.off;
+  RPID_CHECK(ws_check(ctx, o_gemm));
+  uint8_t* Aq = ws_ptr<uint8_t>(ctx, o_Aq);
+  uint8_t* Pq = ws_ptr<uint8_t>(ctx, o_Pq);
+  int* ea = ws_ptr<int>(ctx, o_ea);
+  int* eo = ws_ptr<int>(ctx, o_eo);
+  float* part = ws_ptr<float>(ctx, o_part);
+  if (mq > m) {
+    // zero codes in the padding rows of both operands (mq is a multiple of 128)
+    RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Aq), (size_t)mq * n / 8, 0ull));
+    RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Pq), (size_t)mq * l / 8, 0ull));
+  }
+  hipLaunchKernelGGL(quantize_cols_kernel, dim3((unsigned)n), dim3(256), 0, ctx->stream, A, m, lda,
+                     Aq, mq, ea);
+  RPID_HIP_CHECK(hipGetLastError());
+  int parts = (int)std::min<int64_t>(OMAX_PARTS, (l * m + 255) / 256);
+  hipLaunchKernelGGL(omega_max_kernel, dim3(parts), dim3(256), 0, ctx->stream, Om, l, m, ldo, part);
+  RPID_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(quantize_omega_t_kernel, dim3((unsigned)((m + 31) / 32), (unsigned)((l + 31) / 32)),
+                     dim3(256), 0, ctx->stream, Om, l, m, ldo, part, parts, Pq, mq, eo);
+  RPID_HIP_CHECK(hipGetLastError());
+  RPID_CHECK(sketch_e4m3(ctx, Pq, mq, Aq, mq, mq, n, l, X, ldx, o_gemm));
+  int64_t blocks = (l * n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(unscale_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, X, l, n, ldx,
+                     ea, eo);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
 }
 
 }  // namespace rpid

@@ -121,21 +121,28 @@ __device__ __forceinline__ void wave_argmax(T& v, int& i) {
   }
 }
 
-template <typename T, int R, int NTMAX>
+// R rows per thread, H threads per column (H = 2 for tall panels): workgroup
+// g owns the R*H rows [g R H, (g+1) R H); thread tid = h * kpad + j holds
+// column j of rows g R H + h R + q, q < R.
+template <typename T, int R, int NTMAX, int H>
 __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
   constexpr int W = Words<T>::W;
+  constexpr int RW = R * H;  // rows per workgroup
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int g = blockIdx.x;
   const int G = gridDim.x;
   const int k = a.k;
-  const int64_t row0 = (int64_t)g * R;
+  const int j = (H == 1) ? tid : tid % a.kpad;  // column of this thread
+  const int h = (H == 1) ? 0 : tid / a.kpad;    // row part of this thread
+  const int64_t row0 = (int64_t)g * RW;
   const int lane = tid & 63;
   const int wid = tid >> 6;
 
-  __shared__ T colbuf[R];   // column of the current step, this workgroup's rows
-  __shared__ T mult[R];     // multipliers of the current step (0 for frozen rows)
-  __shared__ int alive[R];  // 1 while the row has not been chosen as a pivot
+  __shared__ T colbuf[RW];  // column of the current step, this workgroup's rows
+  __shared__ T mult[RW];    // multipliers of the current step (0 for frozen rows)
+  __shared__ int alive[RW]; // 1 while the row has not been chosen as a pivot
+  __shared__ T urow[H == 1 ? 1 : NTMAX / H];  // the candidate row (H > 1 only)
   __shared__ int sh_bq;
   __shared__ T sh_best;
   __shared__ int sh_gw;
@@ -147,22 +154,22 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
   // ---- load this workgroup's rows of the panel into registers ------------
   T s[R];
   bool bad = false;
-  if (tid < k) {
+  if (j < k) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int64_t row = row0 + q;
+      const int64_t row = row0 + h * R + q;
       T v = T(0);
-      if (row < a.n) v = a.base[row * a.rs + (int64_t)tid * a.cs];
+      if (row < a.n) v = a.base[row * a.rs + (int64_t)j * a.cs];
       bad |= !isfinite(v);
       s[q] = v;
     }
   }
-  for (int q = tid; q < R; q += nt) alive[q] = (row0 + q < a.n) ? 1 : 0;
-  if (tid == 0) {
+  for (int q = tid; q < RW; q += nt) alive[q] = (row0 + q < a.n) ? 1 : 0;
+  if (j == 0) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) colbuf[q] = s[q];
-    sh_abort = 0;
+    for (int q = 0; q < R; ++q) colbuf[h * R + q] = s[q];
   }
+  if (tid == 0) sh_abort = 0;
   // a non-finite entry anywhere in the slab is published as a NaN candidate
   __shared__ int sh_bad;
   if (tid == 0) sh_bad = 0;
@@ -177,8 +184,8 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     // ---- (1) candidate of this workgroup: one wave over the LDS column ----
     if (wid == 0) {
       T bv = T(-2);
-      int bi = R;
-      for (int q = lane; q < R; q += 64) {
+      int bi = RW;
+      for (int q = lane; q < RW; q += 64) {
         if (alive[q]) {
           T v = fabs(colbuf[q]);
           if (v > bv) {  // ascending q: strict > keeps the smallest index
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       wave_argmax(bv, bi);
       if (lane == 0) {
         sh_bq = bi;
-        T best = (bi < R) ? colbuf[bi] : T(0);  // signed candidate (0: none left)
+        T best = (bi < RW) ? colbuf[bi] : T(0);  // signed candidate (0: none left)
         if (t == 0 && sh_bad) best = T(NAN);
         sh_best = best;
       }
@@ -201,10 +208,12 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     // ---- (2) publish: candidate row and value (tagged words) ---------------
     uint64_t* myrow = a.xrow + ((size_t)par * G + g) * a.kpad * W;
     T myv = T(0);  // this thread's column of the candidate row
-    if (tid >= t && tid < k) {
+    const int hb = bq / R, qb = bq - hb * R;
+    if (h == hb && j >= t && j < k) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) myv = (q == bq) ? s[q] : myv;
-      if (tid > t) put_value(myrow + (size_t)tid * W, myv, tag);
+      for (int q = 0; q < R; ++q) myv = (q == qb) ? s[q] : myv;
+      if (j > t) put_value(myrow + (size_t)j * W, myv, tag);
+      if (H > 1) urow[j] = myv;
     }
     if (tid == 0) put_value(&a.xval[((size_t)par * G + g) * W], sh_best, tag);
 
@@ -268,11 +277,11 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     // the row words are requested first; the divisions overlap their latency
     T uj = T(0);
     bool ok = true;
-    if (!winner && tid > t && tid < k)
-      ok = wait_value(a.xrow + (((size_t)par * G + gw) * a.kpad + tid) * W, tag, uj, a.xflag,
+    if (!winner && j > t && j < k)
+      ok = wait_value(a.xrow + (((size_t)par * G + gw) * a.kpad + j) * W, tag, uj, a.xflag,
                       a.epoch);
-    if (winner) uj = myv;
-    for (int q = tid; q < R; q += nt) {
+    if (winner) uj = (H == 1) ? myv : urow[j < k ? j : 0];
+    for (int q = tid; q < RW; q += nt) {
       const int64_t row = row0 + q;
       const bool is_piv = winner && q == bq;
       const bool live = alive[q] && !is_piv;
@@ -285,7 +294,7 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
         a.J[t] = row0 + bq;
         if (a.diag) a.diag[t] = fabs(pv);
       }
-      if (tid < k) a.Uf[t + (int64_t)tid * a.ldu] = (tid > t) ? myv : (tid == t ? pv : T(0));
+      if (h == 0 && j < k) a.Uf[t + (int64_t)j * a.ldu] = (j > t) ? uj : (j == t ? pv : T(0));
     }
     if (!ok) sh_abort = 1;
     __syncthreads();
@@ -296,12 +305,12 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
 
     // ---- (5) Schur update of this workgroup's rows, columns t+1..k-1 -------
     if (winner && tid == 0) alive[bq] = 0;
-    if (tid > t && tid < k) {
+    if (j > t && j < k) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) s[q] = fma(-mult[q], uj, s[q]);
-      if (tid == t + 1) {
+      for (int q = 0; q < R; ++q) s[q] = fma(-mult[h * R + q], uj, s[q]);
+      if (j == t + 1) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) colbuf[q] = s[q];
+        for (int q = 0; q < R; ++q) colbuf[h * R + q] = s[q];
       }
     }
     __syncthreads();
@@ -337,15 +346,15 @@ int launch_fill_u64(rpid_ctx ctx, uint64_t* p, size_t count, uint64_t value) {
 // VGPRs a thread may spend on its R panel values: one wave per SIMD (256
 // threads) or two (512) leave 256 registers per wave, four (1024) leave 128;
 // the rest is kept for temporaries.
-static constexpr int row_reg_budget(int ntmax) { return ntmax <= 512 ? 160 : 80; }
+static constexpr int row_reg_budget(int ntmax) { return ntmax <= 768 ? 160 : 80; }
 
-template <typename T, int R, int NTMAX>
+template <typename T, int R, int NTMAX, int H>
 static int launch_lupp_R(rpid_ctx ctx, LuppArgs<T> a, int G, int nt) {
   if constexpr (R * (int)sizeof(T) / 4 > row_reg_budget(NTMAX)) {
     return RPID_ERR_UNSUPPORTED;
   } else {
     void* kargs[] = {&a};
-    const void* fn = reinterpret_cast<const void*>(lupp_panel_kernel<T, R, NTMAX>);
+    const void* fn = reinterpret_cast<const void*>(lupp_panel_kernel<T, R, NTMAX, H>);
     int per_cu = 0;
     RPID_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0));
     if (per_cu < 1 || (int64_t)per_cu * ctx->num_cu < G) return RPID_ERR_LAUNCH;
@@ -363,13 +372,13 @@ static int max_rows(int ntmax, int elem_bytes) {
   return r;
 }
 
-template <typename T, int NTMAX>
+template <typename T, int NTMAX, int H>
 static int dispatch_R(rpid_ctx ctx, LuppArgs<T> a, int R, int G, int nt) {
   switch (R) {
-    case 16: return launch_lupp_R<T, 16, NTMAX>(ctx, a, G, nt);
-    case 32: return launch_lupp_R<T, 32, NTMAX>(ctx, a, G, nt);
-    case 64: return launch_lupp_R<T, 64, NTMAX>(ctx, a, G, nt);
-    case 128: return launch_lupp_R<T, 128, NTMAX>(ctx, a, G, nt);
+    case 16: return launch_lupp_R<T, 16, NTMAX, H>(ctx, a, G, nt);
+    case 32: return launch_lupp_R<T, 32, NTMAX, H>(ctx, a, G, nt);
+    case 64: return launch_lupp_R<T, 64, NTMAX, H>(ctx, a, G, nt);
+    case 128: return launch_lupp_R<T, 128, NTMAX, H>(ctx, a, G, nt);
     default: return RPID_ERR_UNSUPPORTED;
   }
 }
@@ -379,23 +388,42 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
                int64_t* J, T* Lf, int64_t ldl, T* Uf, int64_t ldu, T* diag, size_t ws_off,
                int64_t* status_dev) {
   if (k < 1 || k > 1024 || n < k) return RPID_ERR_UNSUPPORTED;
-  const int nt = (int)((k + 63) / 64 * 64);
-  const int ntmax = nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
-  // Rows per workgroup: the smallest R whose grid fits one workgroup per CU
-  // (more rows per workgroup cost registers, fewer cost polling), capped by
-  // the register budget.
-  const int rmax = max_rows(ntmax, (int)sizeof(T));
-  int R = rmax;
-  for (int c = 16; c <= rmax; c *= 2) {
-    if ((n + c - 1) / c <= ctx->num_cu) {
-      R = c;
-      break;
+  const int kpad = (int)((k + 63) / 64 * 64);
+  // Rows per thread: the smallest R whose grid fits one workgroup per CU (more
+  // rows cost registers, fewer cost polling), capped by the register budget.
+  auto pick = [&](int ntmax, int h, int& R, int64_t& G) {
+    const int rmax = max_rows(ntmax, (int)sizeof(T));
+    R = rmax;
+    for (int c = 16; c <= rmax; c *= 2) {
+      if ((n + (int64_t)c * h - 1) / ((int64_t)c * h) <= ctx->num_cu) {
+        R = c;
+        break;
+      }
+    }
+    G = (n + (int64_t)R * h - 1) / ((int64_t)R * h);
+  };
+  int H = 1, nt = kpad;
+  int ntmax = nt <= 256 ? 256 : (nt <= 512 ? 512 : 1024);
+  int R;
+  int64_t G64;
+  pick(ntmax, 1, R, G64);
+  if (G64 > ctx->num_cu && 2 * kpad <= 1024) {
+    // tall panel: two threads per column keep one workgroup per CU
+    const int nt2 = 2 * kpad;
+    const int ntmax2 = nt2 <= 512 ? 512 : (nt2 <= 768 ? 768 : 1024);
+    int R2;
+    int64_t G2;
+    pick(ntmax2, 2, R2, G2);
+    if (G2 < G64) {
+      H = 2;
+      nt = nt2;
+      ntmax = ntmax2;
+      R = R2;
+      G64 = G2;
     }
   }
-  const int64_t G64 = (n + R - 1) / R;
   if (G64 > 4096) return RPID_ERR_UNSUPPORTED;
   const int G = (int)G64;
-  const int kpad = nt;
 
   (void)ws_off;
   constexpr int W = Words<T>::W;
@@ -440,9 +468,14 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   a.xflag = reinterpret_cast<uint64_t*>(ucb + o_flag);
   a.epoch = ctx->lupp_epoch;
   a.status = status_dev;
-  if (ntmax == 256) return dispatch_R<T, 256>(ctx, a, R, G, nt);
-  if (ntmax == 512) return dispatch_R<T, 512>(ctx, a, R, G, nt);
-  return dispatch_R<T, 1024>(ctx, a, R, G, nt);
+  if (H == 1) {
+    if (ntmax == 256) return dispatch_R<T, 256, 1>(ctx, a, R, G, nt);
+    if (ntmax == 512) return dispatch_R<T, 512, 1>(ctx, a, R, G, nt);
+    return dispatch_R<T, 1024, 1>(ctx, a, R, G, nt);
+  }
+  if (ntmax == 512) return dispatch_R<T, 512, 2>(ctx, a, R, G, nt);
+  if (ntmax == 768) return dispatch_R<T, 768, 2>(ctx, a, R, G, nt);
+  return dispatch_R<T, 1024, 2>(ctx, a, R, G, nt);
 }
 
 template int lupp_panel<double>(rpid_ctx, const double*, int64_t, int64_t, int64_t, int64_t,

@@ -113,6 +113,8 @@ int sketch_f64(rpid_ctx ctx, const double* Pt, int64_t ldp, const double* A, int
                int64_t m, int64_t n, int64_t l, double* X, int64_t ldx, size_t ws_off);
 int sketch_f32(rpid_ctx ctx, const float* Pt, int64_t ldp, const float* A, int64_t lda,
                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
+int sketch_e4m3(rpid_ctx ctx, const uint8_t* Pt, int64_t ldp, const uint8_t* A, int64_t lda,
+                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
 int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
 size_t sketch_workspace_bytes(rpid_ctx ctx, int64_t m, int64_t n, int64_t l, int elem_acc);

@@ -25,6 +25,7 @@ namespace rpid {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 
 // Per-dtype traits: element storage, vector width per lane, accumulator.
 template <typename TE>
@@ -62,6 +63,18 @@ struct MT<uint16_t> {  // bf16 storage
   static __device__ __forceinline__ int out_row(int q, int i) { return 4 * q + i; }
 };
 
+template <>
+struct MT<uint8_t> {  // OCP E4M3 storage (FP8)
+  using Acc = float;
+  using AccV = v4f;
+  static constexpr int VEC = 32;    // 32 bytes per lane: the lane's k-values of one MFMA
+  static constexpr int KMFMA = 32;
+  static constexpr int BK = 128;
+  static constexpr int CT = 2;      // 32-byte fragments leave room for two column tiles
+  // same output layout as the BF16 MFMA: register i of lane-group q is row 4 q + i
+  static __device__ __forceinline__ int out_row(int q, int i) { return 4 * q + i; }
+};
+
 template <typename TE>
 struct Frag {
   TE v[MT<TE>::VEC];
@@ -88,6 +101,17 @@ __device__ __forceinline__ v4f mfma_step<uint16_t>(const Frag<uint16_t>& a,
   __builtin_memcpy(&av, a.v, 16);
   __builtin_memcpy(&bv, b.v, 16);
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ v4f mfma_step<uint8_t>(const Frag<uint8_t>& a, const Frag<uint8_t>& b,
+                                                  int s, v4f c) {
+  (void)s;
+  v8i av, bv;
+  __builtin_memcpy(&av, a.v, 32);
+  __builtin_memcpy(&bv, b.v, 32);
+  // both operands E4M3 (format selectors 0), no block scales
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 0, 0, 0);
 }
 
 template <typename TE>
@@ -471,6 +495,10 @@ int sketch_f64(rpid_ctx ctx, const double* Pt, int64_t ldp, const double* A, int
 int sketch_f32(rpid_ctx ctx, const float* Pt, int64_t ldp, const float* A, int64_t lda,
                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
   return sketch_impl<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+}
+int sketch_e4m3(rpid_ctx ctx, const uint8_t* Pt, int64_t ldp, const uint8_t* A, int64_t lda,
+                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+  return sketch_impl<uint8_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
 }
 int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {

@@ -251,6 +251,37 @@ def pin_ties_and_zero_pivot(O):
     assert f["status"] == 3 and f["k_eff"] == 2 and f["J"].tolist() == [0, 1]
 
 
+def pin_e4m3(O):
+    """OCP E4M3 facts: largest finite 448, smallest subnormal 2^-9, smallest
+    normal 2^-6, 127 finite non-negative values; ties go to the even code."""
+    t = O.e4m3_values()
+    assert t.size == 127 and t[-1] == 448.0 and t[1] == 2.0**-9 and t[8] == 2.0**-6
+    assert np.all(np.diff(t) > 0)
+    r = O.e4m3_round(np.array([1.0625, 1.1875, 2.0**-10, 3 * 2.0**-10, -1.0625, 447.0, 0.3]))
+    assert list(r[:6]) == [1.0, 1.25, 0.0, 2.0**-8, -1.0, 448.0]
+    assert r[6] == 0.3125  # 0.3 lies between 0.28125 and 0.3125, nearer the latter
+    for mx, e in ((1.0, 8), (448.0, 0), (449.0, -1), (0.875, 9), (3.5, 7)):
+        assert O.fp8_scale_exp(mx) == e, (mx, e)
+
+
+def pin_sketch_fp8_exact(O, seed=31, m=40, n=9, l=6):
+    """Operands whose scaled values are E4M3 numbers quantise exactly, so the
+    FP8 sketch equals the plain product; a generic operand differs from it by
+    no more than the E4M3 unit roundoff (2^-4) per factor."""
+    rng = np.random.default_rng(seed)
+    A = rng.integers(-7, 8, (m, n)).astype(float)
+    A[0, :] = 7.0  # column maxima 7 -> scale 2^6, and 7 * 2^6 = 448
+    Om = rng.integers(-3, 4, (l, m)).astype(float)
+    Om[0, 0] = 3.0
+    assert np.array_equal(O.sketch_fp8(A, Om), Om @ A)
+    A2 = rng.standard_normal((m, n))
+    Om2 = rng.standard_normal((l, m))
+    err = np.abs(O.sketch_fp8(A2, Om2) - Om2 @ A2)
+    bound = (2 * 2.0**-4 + 2.0**-8) * (np.abs(Om2) @ np.abs(A2)) + 1e-12
+    assert np.all(err <= bound)
+    assert np.abs(O.sketch_fp8(A2, Om2) - Om2 @ A2).max() > 0
+
+
 def pin_scale_invariance(O, seed=13, m=70, n=60, k=7, l=9):
     """Scaling A by 8 (exact in binary floating point) scales X by 8: the
     pivots, Z and every relative residual are unchanged and U scales by 1/8
@@ -284,4 +315,6 @@ ALL_PINS = [
     pin_rangefinder_expectation,
     pin_ties_and_zero_pivot,
     pin_scale_invariance,
+    pin_e4m3,
+    pin_sketch_fp8_exact,
 ]

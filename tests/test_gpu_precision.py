@@ -1,0 +1,154 @@
+"""GPU tests of the precision forms: the FP8 (E4M3) sketch against the FP64
+oracle of the same quantisation, the tall non-negative FP8 workload end to
+end (CUR), the LUPP at the tall workload's full panel size, and the BF16
+path at k = 512 (the Cholesky-QR and inverse kernels beyond registers)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle.rpid_oracle as O  # noqa: E402
+from paper_2104_05877_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[precision]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2104_05877_amd import rpid
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return rpid
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def fp8_bound(A, Om):
+    """FP32 accumulation bound for the E4M3 sketch: 2 m u32 (|Om_q| |A_q|)
+    in the unscaled units (the products of E4M3 values are exact in FP32)."""
+    ea = np.array([O.fp8_scale_exp(np.abs(A[:, j]).max()) for j in range(A.shape[1])])
+    eo = O.fp8_scale_exp(np.abs(Om).max())
+    Aq = np.abs(O.e4m3_round(A * np.ldexp(1.0, ea)[None, :]))
+    Oq = np.abs(O.e4m3_round(Om * np.ldexp(1.0, eo)))
+    m = A.shape[0]
+    return 2 * m * 2.0**-24 * (Oq @ Aq) * np.ldexp(1.0, -(eo + ea))[None, :]
+
+
+@pytest.mark.parametrize("m,n,l,seed", [(1000, 800, 50, 1), (4096, 515, 400, 2), (777, 33, 17, 3),
+                                        (65536, 96, 400, 4)])
+def test_sketch_fp8_parity(R, ctx, m, n, l, seed):
+    """E4M3 sketch with per-column and global power-of-two scales vs the
+    oracle's exact product of the same quantised values (ragged m is padded
+    with zero codes; l = 400 spans two row chunks)."""
+    say("sketch fp8", m, n, l)
+    rng = np.random.default_rng(seed)
+    A = (rng.standard_normal((m, n)) * 10.0 ** rng.uniform(-3, 3, n)[None, :]).astype(np.float32)
+    Om = rng.standard_normal((l, m)).astype(np.float32)
+    Ad = inputs.torch_colmajor(A, torch.float32, "cuda")
+    Od = inputs.torch_colmajor(Om, torch.float32, "cuda")
+    X = host(R.rpid_sketch_fp8(ctx, Ad, Od))
+    ref = O.sketch_fp8(A.astype(np.float64), Om.astype(np.float64))
+    bound = fp8_bound(A.astype(np.float64), Om.astype(np.float64))
+    assert np.all(np.abs(X - ref) <= bound + 1e-300)
+
+
+def test_sketch_fp8_tall_full_size_sampled(R, ctx):
+    """The tall workload at full size (65536 x 4096, l = 400): sampled
+    columns of X against the oracle, which needs only those columns of A."""
+    m, n, r, l = 65536, 4096, 384, 400
+    say("sketch fp8 full size", m, n, l)
+    Ad = inputs.torch_nonneg_lowrank(m, n, r, 1e-3, 5, "cuda")
+    Od = inputs.torch_gaussian(l, m, 6, "cuda", dtype=torch.float32)
+    X = R.rpid_sketch_fp8(ctx, Ad, Od)
+    cols = np.array([0, 1, 17, 1000, 2047, 2048, 3001, 4095])
+    A = Ad[:, torch.tensor(cols, device="cuda")].double().cpu().numpy()
+    Om = Od.double().cpu().numpy()
+    ref = O.sketch_fp8(A, Om)
+    Xs = host(X)[:, cols]
+    assert np.all(np.abs(Xs - ref) <= fp8_bound(A, Om) + 1e-300)
+
+
+def test_lupp_tall_panel_invariants(R, ctx):
+    """FP32 LUPP of a 384 x 65536 panel (512 workgroups, two per CU): pivots
+    distinct, |L'| <= 1 with unit pivots, and X^T(:, 0:k) = L' U' (the row
+    order of L' is the original one) to FP32 accuracy."""
+    l, n, k = 384, 65536, 384
+    say("lupp tall panel", l, n, k)
+    X = inputs.torch_gaussian(l, n, 21, "cuda", dtype=torch.float32)
+    J, Lf, Uf, diag, keff, st = R.rpid_select_columns(ctx, X, k)
+    assert st == 0 and keff == k
+    Jh = J.cpu().numpy()
+    assert len(np.unique(Jh)) == k
+    L_ = host(Lf)
+    assert np.abs(L_).max() <= 1.0 + 1e-6
+    assert np.all(L_[Jh, np.arange(k)] == 1.0)
+    U_ = host(Uf)
+    Xt = host(X)[:k].T
+    err = np.abs(Xt - L_ @ U_).max() / np.abs(Xt).max()
+    say("reconstruction", err)
+    assert err < 1e-3
+
+
+def test_tall_fp8_cur_end_to_end(R, ctx):
+    """A scaled-down tall non-negative workload: FP8 sketch, FP32 LUPP, CUR
+    from the FP32 values.  The CUR residual stays within 1.05x of the oracle
+    running the same FP8 quantisation in FP64, or within the spread of the
+    oracle over five sketches (the residual sits at the noise floor)."""
+    m, n, r, k, l = 8192, 1024, 64, 64, 72
+    say("tall fp8 cur", m, n, k, l)
+    Ad = inputs.torch_nonneg_lowrank(m, n, r, 1e-3, 7, "cuda")
+    A = Ad.double().cpu().numpy()
+    res_o = []
+    for s in range(5):
+        Od = inputs.torch_gaussian(l, m, 30 + s, "cuda", dtype=torch.float32)
+        Om = Od.double().cpu().numpy()
+        X = O.sketch_fp8(A, Om)
+        J = O.lupp_colwise(X, k)["J"]
+        I = O.lupp_rowwise(A[:, J], k)["J"]
+        U = O.cur_u(A, J, I)
+        res_o.append(O.residuals(A, J, I=I, U=U, only=("cur",))["cur"])
+        if s == 0:
+            Xg = R.rpid_sketch_fp8(ctx, Ad, Od)
+            Jg, Lf, Uf, diag, keff, st = R.rpid_select_columns(ctx, Xg, k)
+            assert st == 0
+            Ig, Ug, keff_i, st_i = R.rpid_cur(ctx, Ad, k, Jg)
+            assert st_i == 0
+            rg = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, k, Jg, I=Ig, U=Ug)
+    say("gpu", rg, "oracle", res_o)
+    assert rg <= 1.05 * res_o[0] or rg <= max(res_o)
+
+
+def test_bf16_k512_end_to_end(R, ctx):
+    """BF16 storage at k = 512, l = 544 (LUPP with 512 columns, Cholesky-QR and
+    triangular inverses beyond the register-resident size): ID and CUR
+    residuals within 1.05x of the FP64 oracle on the same stored values."""
+    m, n, k, l = 4096, 3000, 512, 544
+    say("bf16 k512", m, n, k, l)
+    A64 = inputs.torch_lowrank_noise(m, n, k, 1e-4, 9, "cuda")
+    Ab = A64.T.contiguous().bfloat16().T
+    Ob = inputs.torch_gaussian(l, m, 10, "cuda").T.contiguous().bfloat16().T
+    g = R.decompose(ctx, Ab, Ob, k)
+    assert g["status"] == 0 and g["status_I"] == 0
+    rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ab, k, g["J"], Z=g["Z"])
+    rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ab, k, g["J"], I=g["I"], U=g["U"])
+    A = host(Ab)
+    o = O.decompose(A, host(Ob), k)
+    ro = O.residuals(A, o["J"], Z=o["Z"], I=o["I"], U=o["U"], only=("id", "cur"))
+    say("gpu", rid, rcur, "oracle", ro["id"], ro["cur"])
+    assert rid <= 1.05 * ro["id"] and rcur <= 1.05 * ro["cur"]

@@ -51,6 +51,11 @@ MUTANTS = {
     "eta without the identity block": ("return float(np.sqrt(1.0 + s * s))", "return float(np.sqrt(s * s))"),
     "id residual not relative": ('out["id"] = nrm(A - C @ _f64(Z)) / na', 'out["id"] = nrm(A - C @ _f64(Z))'),
     "CUR with R transposed factor": ('qr_, rr = np.linalg.qr(R.T)', 'qr_, rr = np.linalg.qr(R.T[:, ::-1])'),
+    "E4M3 ties away from zero": ("pick_hi = (dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0))",
+                                 "pick_hi = (dhi <= dlo)"),
+    "FP8 scale one step high": ("    while np.ldexp(mx, e) > E4M3_MAX:\n        e -= 1\n    return e",
+                                "    while np.ldexp(mx, e) > E4M3_MAX:\n        e -= 1\n    return e + 1"),
+    "FP8 sketch not unscaled": ("return (Oq @ Aq) * np.ldexp(1.0, -(eo + ea))[None, :]", "return Oq @ Aq"),
 }
 
 
