@@ -143,67 +143,83 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
   __shared__ T mult[RW];    // multipliers of the current step (0 for frozen rows)
   __shared__ int alive[RW]; // 1 while the row has not been chosen as a pivot
   __shared__ T urow[H == 1 ? 1 : NTMAX / H];  // the candidate row (H > 1 only)
-  __shared__ int sh_bq;
-  __shared__ T sh_best;
+  __shared__ T cand_abs[H], cand_val[H];      // next step's candidate of each row part
+  __shared__ int cand_row[H];
   __shared__ int sh_gw;
   __shared__ T sh_pv;
   __shared__ int sh_code;   // 0 go on, 1 stop: status in sh_status
   __shared__ int64_t sh_status;
   __shared__ int sh_abort;
+  __shared__ int sh_bad;
 
   // ---- load this workgroup's rows of the panel into registers ------------
+  // A row that has been a pivot is never read again (its U row is published
+  // at its step and its later multipliers are 0), so its registers are set to
+  // zero: the candidate search then needs no list of remaining rows (a zero
+  // can only win where every remaining candidate is zero, which stops the
+  // factorisation as an exactly zero pivot).  Rows beyond n load as zeros.
   T s[R];
   bool bad = false;
-  if (j < k) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int64_t row = row0 + h * R + q;
+    T v = T(0);
+    if (row < a.n && j < k) v = a.base[row * a.rs + (int64_t)j * a.cs];
+    bad |= !isfinite(v);
+    s[q] = v;
+  }
+  // the candidate of the owned column among this thread's rows (largest
+  // modulus, the smallest row on ties)
+  auto local_candidate = [&]() {
+    T bv = T(-1), bs = T(0);
+    int bi = h * R;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int64_t row = row0 + h * R + q;
-      T v = T(0);
-      if (row < a.n) v = a.base[row * a.rs + (int64_t)j * a.cs];
-      bad |= !isfinite(v);
-      s[q] = v;
+      const T v = fabs(s[q]);
+      if (v > bv) {
+        bv = v;
+        bi = h * R + q;
+        bs = s[q];
+      }
     }
-  }
+    cand_abs[h] = bv;
+    cand_row[h] = bi;
+    cand_val[h] = bs;
+  };
   for (int q = tid; q < RW; q += nt) alive[q] = (row0 + q < a.n) ? 1 : 0;
   if (j == 0) {
 #pragma unroll
     for (int q = 0; q < R; ++q) colbuf[h * R + q] = s[q];
+    local_candidate();
   }
-  if (tid == 0) sh_abort = 0;
-  // a non-finite entry anywhere in the slab is published as a NaN candidate
-  __shared__ int sh_bad;
-  if (tid == 0) sh_bad = 0;
+  if (tid == 0) {
+    sh_abort = 0;
+    sh_bad = 0;
+  }
   __syncthreads();
-  if (__any(bad) && lane == 0) sh_bad = 1;
+  // a non-finite entry anywhere in the slab is published as a NaN candidate
+  if (__any(bad && j < k) && lane == 0) sh_bad = 1;
   __syncthreads();
 
   int64_t final_status = 0;
   for (int t = 0; t < k; ++t) {
     const int par = t & 1;
     const unsigned tag = step_tag(a.epoch, t);
-    // ---- (1) candidate of this workgroup: one wave over the LDS column ----
-    if (wid == 0) {
-      T bv = T(-2);
-      int bi = RW;
-      for (int q = lane; q < RW; q += 64) {
-        if (alive[q]) {
-          T v = fabs(colbuf[q]);
-          if (v > bv) {  // ascending q: strict > keeps the smallest index
-            bv = v;
-            bi = q;
-          }
+    // ---- (1) this workgroup's candidate (prepared at the end of last step) --
+    int bq = cand_row[0];
+    T best = cand_val[0];
+    if (H > 1) {
+      T ba = cand_abs[0];
+#pragma unroll
+      for (int p = 1; p < H; ++p) {
+        if (cand_abs[p] > ba) {  // ties keep the earlier part (smaller rows)
+          ba = cand_abs[p];
+          bq = cand_row[p];
+          best = cand_val[p];
         }
       }
-      wave_argmax(bv, bi);
-      if (lane == 0) {
-        sh_bq = bi;
-        T best = (bi < RW) ? colbuf[bi] : T(0);  // signed candidate (0: none left)
-        if (t == 0 && sh_bad) best = T(NAN);
-        sh_best = best;
-      }
     }
-    __syncthreads();
-    const int bq = sh_bq;
+    if (t == 0 && sh_bad) best = T(NAN);
 
     // ---- (2) publish: candidate row and value (tagged words) ---------------
     uint64_t* myrow = a.xrow + ((size_t)par * G + g) * a.kpad * W;
@@ -215,24 +231,62 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       if (j > t) put_value(myrow + (size_t)j * W, myv, tag);
       if (H > 1) urow[j] = myv;
     }
-    if (tid == 0) put_value(&a.xval[((size_t)par * G + g) * W], sh_best, tag);
+    if (tid == 0) put_value(&a.xval[((size_t)par * G + g) * W], best, tag);
 
     // ---- (3) wave 0 gathers every workgroup's value and reduces ------------
+    //      (all of a lane's words are requested at once; only missing ones
+    //      are requested again)
     if (wid == 0) {
       T cv = T(-2), cpv = T(0);
       int ci = 0x7fffffff;
       bool ok = true, nonfinite = false;
-      for (int i = lane; i < G && ok; i += 64) {
-        T v;
-        ok = wait_value(&a.xval[((size_t)par * G + i) * W], tag, v, a.xflag, a.epoch);
-        if (ok) {
-          if (!isfinite(v)) nonfinite = true;
-          const T av = fabs(v);
-          if (av > cv || (av == cv && i < ci)) {
-            cv = av;
-            ci = i;
-            cpv = v;
+      auto consider = [&](int i, T v) {
+        if (!isfinite(v)) nonfinite = true;
+        const T av = fabs(v);
+        if (av > cv || (av == cv && i < ci)) {
+          cv = av;
+          ci = i;
+          cpv = v;
+        }
+      };
+      constexpr int PMAX = 4;
+      if (G <= 64 * PMAX) {
+        unsigned want = 0, got = 0, spins = 0;
+#pragma unroll
+        for (int c = 0; c < PMAX; ++c)
+          if (lane + 64 * c < G) want |= 1u << c;
+        T vals[PMAX];
+        while (got != want) {
+#pragma unroll
+          for (int c = 0; c < PMAX; ++c) {
+            if (((want & ~got) >> c) & 1u) {
+              T v;
+              if (try_value(&a.xval[((size_t)par * G + lane + 64 * c) * W], tag, v)) {
+                vals[c] = v;
+                got |= 1u << c;
+              }
+            }
           }
+          if (got == want) break;
+          if ((++spins & 255u) == 0) {
+            if ((unsigned)wload(a.xflag) == a.epoch || spins > kSpinLimit) {
+              wstore(a.xflag, (uint64_t)a.epoch);
+              ok = false;
+              break;
+            }
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok) {
+#pragma unroll
+          for (int c = 0; c < PMAX; ++c)
+            if ((want >> c) & 1u) consider(lane + 64 * c, vals[c]);
+        }
+      } else {
+        for (int i = lane; i < G && ok; i += 64) {
+          T v;
+          ok = wait_value(&a.xval[((size_t)par * G + i) * W], tag, v, a.xflag, a.epoch);
+          if (ok) consider(i, v);
         }
       }
       const bool any_fail = __any(!ok);
@@ -295,6 +349,10 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
         if (a.diag) a.diag[t] = fabs(pv);
       }
       if (h == 0 && j < k) a.Uf[t + (int64_t)j * a.ldu] = (j > t) ? uj : (j == t ? pv : T(0));
+      if (h == hb) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) s[q] = (q == qb) ? T(0) : s[q];
+      }
     }
     if (!ok) sh_abort = 1;
     __syncthreads();
@@ -303,7 +361,8 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       break;
     }
 
-    // ---- (5) Schur update of this workgroup's rows, columns t+1..k-1 -------
+    // ---- (5) Schur update of this workgroup's rows, columns t+1..k-1; the
+    //      owners of column t+1 mirror it and pick the next candidate --------
     if (winner && tid == 0) alive[bq] = 0;
     if (j > t && j < k) {
 #pragma unroll
@@ -311,6 +370,7 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       if (j == t + 1) {
 #pragma unroll
         for (int q = 0; q < R; ++q) colbuf[h * R + q] = s[q];
+        local_candidate();
       }
     }
     __syncthreads();
@@ -424,12 +484,13 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   }
   if (G64 > 4096) return RPID_ERR_UNSUPPORTED;
   const int G = (int)G64;
+  const int xstride = kpad;  // words per published row
 
   (void)ws_off;
   constexpr int W = Words<T>::W;
   Carve cv;
   const size_t o_val = cv.take<uint64_t>((size_t)2 * G * W);
-  const size_t o_row = cv.take<uint64_t>((size_t)2 * G * kpad * W);
+  const size_t o_row = cv.take<uint64_t>((size_t)2 * G * xstride * W);
   const size_t o_flag = cv.take<uint64_t>(1);
   bool fresh = false;
   if (cv.off > ctx->uc_bytes) {
