@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--only-main", action="store_true", help="time the main mode only")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank report")
     ap.add_argument("--input-cache", default=None,
                     help="folder: load the FP32 workload from it if stored there, else "
                          "generate it and store it (lets profiled runs skip the QR-based "
@@ -238,6 +239,67 @@ def cpu_baseline(torch, A, Om):
     return dict(seconds=t, threads=threads, rid=r["id"], rcur=r["cur"], J=d["J"], I=d["I"])
 
 
+# learned-rank report: a seeded stream of matrices with exponential or
+# polynomial spectra; tolerance 1e-4 on the relative ID residual
+LEARN = dict(m_range=(1024, 2048), n_range=(1024, 2048), rate_range=(0.1, 1.0),
+             power_range=(2.5, 6.0))
+LEARN_TOL, LEARN_LMAX, LEARN_TRAIN, LEARN_TEST = 1e-4, 128, 128, 48
+
+
+def learned_report(torch, ctx):
+    """Train the rank network on LEARN_TRAIN matrices of the stream (labels
+    from the plain FP64 path), then reach the tolerance on LEARN_TEST held-out
+    matrices two ways: the BF16-profile network with the plain path as
+    fallback, and the plain FP64 path with rank doubling from 8.  Both answers
+    are judged by the FP64 residual; times are wall-clock per matrix."""
+    import numpy as np
+
+    from paper_2104_05877_amd import inputs, learned as Lr
+
+    feats, targets, labels = [], [], []
+    for idx in range(LEARN_TRAIN):
+        A64, Om64, A16, Om16, _ = inputs.torch_stream_case(idx, LEARN_LMAX, "cuda", 1, **LEARN)
+        k, _ = Lr.rank_label(ctx, A64, Om64, LEARN_TOL, LEARN_LMAX)
+        feats.append(Lr.profile_features(ctx, A16, Om16, LEARN_LMAX))
+        labels.append(k)
+        targets.append(Lr.target_of(k, LEARN_LMAX))
+    net = Lr.RankNet(ctx, seed=1)
+    t0 = time.perf_counter()
+    hist = net.fit(torch.stack(feats), torch.tensor(targets, dtype=torch.float32, device="cuda"),
+                   epochs=300, batch=32, lr=2e-3, tau=0.9, seed=2)
+    t_train = time.perf_counter() - t0
+    res = dict(learned=[], doubling=[], att_l=[], att_d=[], khat=[], kfin=[], kstar=[], met=0)
+    for idx in range(10000, 10000 + LEARN_TEST):
+        A64, Om64, A16, Om16, _ = inputs.torch_stream_case(idx, LEARN_LMAX, "cuda", 1, **LEARN)
+        kd, ed, sd = Lr.solve_doubling(ctx, A64, Om64, LEARN_TOL, 8, LEARN_LMAX)
+        kl, el, sl, khat = Lr.solve_learned(ctx, net, A64, Om64, A16, Om16, LEARN_TOL, LEARN_LMAX,
+                                            LEARN_LMAX)
+        ks, _ = Lr.rank_label(ctx, A64, Om64, LEARN_TOL, LEARN_LMAX)
+        res["learned"].append(sl)
+        res["doubling"].append(sd)
+        res["att_l"].append(el)
+        res["att_d"].append(ed)
+        if kl is not None and ks is not None:
+            res["khat"].append(khat / ks)
+            res["kfin"].append(kl / ks)
+        res["met"] += int(kl is not None and khat >= kl)
+    return {
+        "workload": "stream of %d + %d matrices, m, n in [%d, %d], exp rate in [%g, %g] or poly power "
+                    "in [%g, %g], tol %g, l = %d" % (LEARN_TRAIN, LEARN_TEST, *LEARN["m_range"],
+                                                     *LEARN["rate_range"], *LEARN["power_range"],
+                                                     LEARN_TOL, LEARN_LMAX),
+        "train_loss_first_last": [hist[0], hist[-1]], "train_seconds": t_train,
+        "ms_per_matrix_learned": 1e3 * float(np.mean(res["learned"])),
+        "ms_per_matrix_fp64_doubling": 1e3 * float(np.mean(res["doubling"])),
+        "speedup_learned_vs_fp64_doubling": float(np.sum(res["doubling"]) / np.sum(res["learned"])),
+        "fp64_attempts_learned": float(np.mean(res["att_l"])),
+        "fp64_attempts_doubling": float(np.mean(res["att_d"])),
+        "met_without_fallback": res["met"] / LEARN_TEST,
+        "khat_over_kstar_median": float(np.median(res["khat"])) if res["khat"] else None,
+        "kfinal_over_kstar_median": float(np.median(res["kfin"])) if res["kfin"] else None,
+    }
+
+
 def main():
     args = parse()
     if args.summarize_counters:
@@ -331,6 +393,9 @@ def main():
                             "ms_p10_p50_p90": r["decomp_ms_p10_p50_p90"]} for m, r in results.items()},
         "roofline": roof,
     }
+    if not args.no_learned and not args.only_main:
+        log("learned-rank report")
+        line["learned_rank"] = learned_report(torch, ctx)
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on one decomposition of the same workload")
         A, Om = data[args.mode]
