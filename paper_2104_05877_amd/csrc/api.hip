@@ -74,28 +74,57 @@ static size_t esize(rpid_dtype t) {
   return 0;
 }
 
-// Transpose-copy for the packing of Omega (element size 2, 4 or 8 bytes).
+// Transpose-copy for the packing of Omega (element size 2, 4 or 8 bytes):
+// Y(j, i) = X(i, j), X rows x cols and Y cols x rows, both column-major.
+// 64 x 64 tiles through LDS; 16-byte vectors on both sides of an interior,
+// aligned tile, element by element at the edges.
 template <typename E>
-__global__ void transpose_copy_kernel(int64_t rows, int64_t cols, const E* X, int64_t ldx, E* Y,
-                                      int64_t ldy) {
-  __shared__ E tile[32][33];
-  const int64_t bi = (int64_t)blockIdx.x * 32, bj = (int64_t)blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t i = bi + tx, j = bj + r;
-    if (i < rows && j < cols) tile[r][tx] = X[i + j * ldx];
+__global__ __launch_bounds__(256) void transpose_copy_kernel(int64_t rows, int64_t cols, const E* X,
+                                                             int64_t ldx, E* Y, int64_t ldy) {
+  constexpr int T = 64;
+  constexpr int V = 16 / (int)sizeof(E);  // elements per 16-byte vector
+  constexpr int LD = T + V;               // padded LDS column
+  __shared__ __attribute__((aligned(16))) E tile[T * LD];
+  const int64_t bi = (int64_t)blockIdx.x * T, bj = (int64_t)blockIdx.y * T;
+  const bool full = bi + T <= rows && bj + T <= cols;
+  const bool vx = full && ((uintptr_t)X % 16 == 0) && (ldx * (int64_t)sizeof(E)) % 16 == 0;
+  const bool vy = full && ((uintptr_t)Y % 16 == 0) && (ldy * (int64_t)sizeof(E)) % 16 == 0;
+  const int tid = threadIdx.x;
+  // load: tile(j, i) = X(bi + i, bj + j)
+  if (vx) {
+    for (int v = tid; v < T * T / V; v += 256) {
+      const int j = v / (T / V), i = (v % (T / V)) * V;
+      *reinterpret_cast<uint4*>(&tile[j * LD + i]) =
+          *reinterpret_cast<const uint4*>(X + (bi + i) + (bj + j) * ldx);
+    }
+  } else {
+    for (int e = tid; e < T * T; e += 256) {
+      const int j = e / T, i = e % T;
+      if (bi + i < rows && bj + j < cols) tile[j * LD + i] = X[(bi + i) + (bj + j) * ldx];
+    }
   }
   __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t j = bj + tx, i = bi + r;
-    if (i < rows && j < cols) Y[j + i * ldy] = tile[tx][r];
+  // store: Y(bj + j, bi + i) = tile(j, i); a vector holds V consecutive j
+  if (vy) {
+    for (int v = tid; v < T * T / V; v += 256) {
+      const int i = v / (T / V), j = (v % (T / V)) * V;
+      E buf[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) buf[u] = tile[(j + u) * LD + i];
+      *reinterpret_cast<uint4*>(Y + (bj + j) + (bi + i) * ldy) = *reinterpret_cast<const uint4*>(buf);
+    }
+  } else {
+    for (int e = tid; e < T * T; e += 256) {
+      const int i = e / T, j = e % T;
+      if (bi + i < rows && bj + j < cols) Y[(bj + j) + (bi + i) * ldy] = tile[j * LD + i];
+    }
   }
 }
 
 template <typename E>
 static int transpose_copy(rpid_ctx ctx, int64_t rows, int64_t cols, const E* X, int64_t ldx, E* Y,
                           int64_t ldy) {
-  dim3 grid((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32));
+  dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
   hipLaunchKernelGGL((transpose_copy_kernel<E>), grid, dim3(256), 0, ctx->stream, rows, cols, X,
                      ldx, Y, ldy);
   RPID_HIP_CHECK(hipGetLastError());
@@ -427,7 +456,7 @@ int rpid_sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t 
   if (!X) return -9;
   if (ldx < l) return -10;
   RPID_HIP_CHECK(hipSetDevice(ctx->device));
-  const int64_t mq = (m + 127) / 128 * 128;
+  const int64_t mq = (m + 511) / 512 * 512;
   RPID_CHECK(ensure_workspace(ctx, sketch_fp8_workspace(m, n, l) +
                                        sketch_workspace_bytes(ctx, mq, n, l, 4)));
   return sketch_fp8(ctx, A, m, n, lda, Omega, l, ldo, X, ldx, 0);

@@ -144,16 +144,16 @@ constexpr int OMAX_PARTS = 512;
 }  // namespace
 
 size_t sketch_fp8_workspace(int64_t m, int64_t n, int64_t l) {
-  const int64_t mq = (m + 127) / 128 * 128;  // quantised rows padded to the MFMA depth
+  const int64_t mq = (m + 511) / 512 * 512;  // quantised rows padded to whole stage pairs
   return (size_t)mq * n + (size_t)mq * l + (size_t)n * sizeof(int) + 64 +
          OMAX_PARTS * sizeof(float) + 4096;
 }
 
 int sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, const float* Om,
                int64_t l, int64_t ldo, float* X, int64_t ldx, size_t ws_off) {
-  // quantised copies padded with zero codes to a multiple of 128 rows, so the
-  // pipelined kernel (whole 128-deep stages, 16-byte aligned) always applies
-  const int64_t mq = (m + 127) / 128 * 128;
+  // quantised copies padded with zero codes to a multiple of 512 rows, so the
+  // streaming kernel (pairs of 256-deep stages, 16-byte aligned) applies
+  const int64_t mq = (m + 511) / 512 * 512;
   Carve cv;
   cv.off = ws_off;
   const size_t o_Aq = cv.take<uint8_t>((size_t)mq * n);
@@ -169,7 +169,7 @@ int sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, 
   int* eo = ws_ptr<int>(ctx, o_eo);
   float* part = ws_ptr<float>(ctx, o_part);
   if (mq > m) {
-    // zero codes in the padding rows of both operands (mq is a multiple of 128)
+    // zero codes in the padding rows of both operands (mq is a multiple of 512)
     RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Aq), (size_t)mq * n / 8, 0ull));
     RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Pq), (size_t)mq * l / 8, 0ull));
   }

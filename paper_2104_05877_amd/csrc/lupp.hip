@@ -90,6 +90,18 @@ __device__ __forceinline__ bool try_value(const uint64_t* p, unsigned tag, doubl
   return true;
 }
 
+// Value of a word set already known to carry the step's tag.
+template <typename T>
+__device__ __forceinline__ T word_value(const uint64_t* w);
+template <>
+__device__ __forceinline__ float word_value<float>(const uint64_t* w) {
+  return __uint_as_float((unsigned)w[0]);
+}
+template <>
+__device__ __forceinline__ double word_value<double>(const uint64_t* w) {
+  return __longlong_as_double((long long)((w[0] << 32) | (w[1] & 0xffffffffull)));
+}
+
 // Spin until the tagged word(s) at p carry `tag`; false if the launch was
 // aborted (another workgroup timed out) or this wait exceeded the spin limit.
 template <typename V>
@@ -169,22 +181,30 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     s[q] = v;
   }
   // the candidate of the owned column among this thread's rows (largest
-  // modulus, the smallest row on ties)
+  // modulus, the smallest row on ties), by a pairwise tree: a pair keeps its
+  // right (larger-row) entry only if that entry is strictly larger
   auto local_candidate = [&]() {
-    T bv = T(-1), bs = T(0);
-    int bi = h * R;
+    T av[R], sv[R];
+    int iv[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const T v = fabs(s[q]);
-      if (v > bv) {
-        bv = v;
-        bi = h * R + q;
-        bs = s[q];
+      av[q] = fabs(s[q]);
+      sv[q] = s[q];
+      iv[q] = q;
+    }
+#pragma unroll
+    for (int w = 1; w < R; w *= 2) {
+#pragma unroll
+      for (int q = 0; q + w < R; q += 2 * w) {
+        const bool right = av[q + w] > av[q];
+        av[q] = right ? av[q + w] : av[q];
+        sv[q] = right ? sv[q + w] : sv[q];
+        iv[q] = right ? iv[q + w] : iv[q];
       }
     }
-    cand_abs[h] = bv;
-    cand_row[h] = bi;
-    cand_val[h] = bs;
+    cand_abs[h] = av[0];
+    cand_row[h] = h * R + iv[0];
+    cand_val[h] = sv[0];
   };
   for (int q = tid; q < RW; q += nt) alive[q] = (row0 + q < a.n) ? 1 : 0;
   if (j == 0) {
@@ -221,7 +241,10 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     }
     if (t == 0 && sh_bad) best = T(NAN);
 
-    // ---- (2) publish: candidate row and value (tagged words) ---------------
+    // ---- (2) publish: candidate value, then the candidate row (tagged
+    //      words; the value goes first so that it does not queue behind the
+    //      row's stores) ------------------------------------------------------
+    if (tid == 0) put_value(&a.xval[((size_t)par * G + g) * W], best, tag);
     uint64_t* myrow = a.xrow + ((size_t)par * G + g) * a.kpad * W;
     T myv = T(0);  // this thread's column of the candidate row
     const int hb = bq / R, qb = bq - hb * R;
@@ -231,11 +254,10 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       if (j > t) put_value(myrow + (size_t)j * W, myv, tag);
       if (H > 1) urow[j] = myv;
     }
-    if (tid == 0) put_value(&a.xval[((size_t)par * G + g) * W], best, tag);
 
     // ---- (3) wave 0 gathers every workgroup's value and reduces ------------
-    //      (all of a lane's words are requested at once; only missing ones
-    //      are requested again)
+    //      (all of a lane's words are requested at once, and a second round
+    //      of requests is in flight while the first is checked)
     if (wid == 0) {
       T cv = T(-2), cpv = T(0);
       int ci = 0x7fffffff;
@@ -256,27 +278,53 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
         for (int c = 0; c < PMAX; ++c)
           if (lane + 64 * c < G) want |= 1u << c;
         T vals[PMAX];
-        while (got != want) {
+        uint64_t wa[W * PMAX], wb[W * PMAX];
+        // every round requests all PMAX words of the lane (indices past G
+        // read word G-1 and are ignored): a fixed number of loads per round,
+        // so the second round can stay in flight while the first is checked
+        const uint64_t* xw[PMAX];
 #pragma unroll
-          for (int c = 0; c < PMAX; ++c) {
-            if (((want & ~got) >> c) & 1u) {
-              T v;
-              if (try_value(&a.xval[((size_t)par * G + lane + 64 * c) * W], tag, v)) {
-                vals[c] = v;
+        for (int c = 0; c < PMAX; ++c)
+          xw[c] = &a.xval[((size_t)par * G + min(lane + 64 * c, G - 1)) * W];
+        auto request = [&](uint64_t(&w)[W * PMAX]) {
+#pragma unroll
+          for (int c = 0; c < PMAX; ++c)
+#pragma unroll
+            for (int e = 0; e < W; ++e) w[c * W + e] = wload(xw[c] + e);
+        };
+        // accept the words of a set that carry this step's tag
+        auto accept = [&](const uint64_t(&w)[W * PMAX], unsigned asked) {
+#pragma unroll
+          for (int c = 0; c < PMAX; ++c)
+            if ((asked >> c) & 1u) {
+              bool fresh = true;
+#pragma unroll
+              for (int e = 0; e < W; ++e) fresh &= (unsigned)(w[c * W + e] >> 32) == tag;
+              if (fresh) {
+                vals[c] = word_value<T>(&w[c * W]);
                 got |= 1u << c;
               }
             }
-          }
+        };
+        request(wa);
+        while (true) {
+          request(wb);
+          accept(wa, want & ~got);
           if (got == want) break;
-          if ((++spins & 255u) == 0) {
-            if ((unsigned)wload(a.xflag) == a.epoch || spins > kSpinLimit) {
+          request(wa);
+          accept(wb, want & ~got);
+          if (got == want) break;
+          if ((++spins & 127u) == 0) {
+            if ((unsigned)wload(a.xflag) == a.epoch || spins > kSpinLimit / 2) {
               wstore(a.xflag, (uint64_t)a.epoch);
               ok = false;
               break;
             }
           }
-          __builtin_amdgcn_s_sleep(1);
         }
+        // the set still in flight is not used again; wait for it before its
+        // registers are reused
+        __builtin_amdgcn_s_waitcnt(0);
         if (ok) {
 #pragma unroll
           for (int c = 0; c < PMAX; ++c)

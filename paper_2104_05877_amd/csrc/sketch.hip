@@ -141,9 +141,11 @@ struct SketchArgs {
   int split;       // number of K-ranges
   int64_t kchunk;  // K per range (multiple of BK)
   int ltiles;      // row tiles (of 16) per l-chunk
-  typename MT<TE>::Acc* out;  // partials [split][lchunks*16*ltiles? no: n x ldo] or X
+  typename MT<TE>::Acc* out;  // split-K partials (split slices of l x n) or X itself
   int64_t ldo;                // leading dimension of out (rows)
   int64_t out_split_stride;   // elements between split slices (0 if split == 1)
+  int64_t kpairs;             // streaming kernel: K in stages, shared out evenly
+  int vec_out;                // streaming kernel: out rows writable as 4-element vectors
 };
 
 template <typename TE, int RT, bool ALIGNED>
@@ -174,7 +176,6 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchArgs<TE> a) {
   const int lchunk = (int)(rest / ncolstrips);
 
   const int row_base = lchunk * ROWS;
-  const int rt_act = min(RT, (a.l - row_base + 15) / 16);
   const int64_t kbeg = (int64_t)split_id * a.kchunk;
   const int64_t kend = min(a.m, kbeg + a.kchunk);
   const int64_t col_base = (int64_t)strip * (4 * CT * 16) + wid * (CT * 16);
@@ -234,14 +235,12 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchArgs<TE> a) {
       }
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        if (r < rt_act) {
-          Frag<TE> af;
-          load_frag(af, &lds[buf][(r * 16 + c16) * LROW + sub * 4 * VEC + q * VEC]);
+        Frag<TE> af;
+        load_frag(af, &lds[buf][(r * 16 + c16) * LROW + sub * 4 * VEC + q * VEC]);
 #pragma unroll
-          for (int s = 0; s < VEC / M::KMFMA; ++s)
+        for (int s = 0; s < VEC / M::KMFMA; ++s)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) acc[r][c] = mfma_step<TE>(af, bf[c], s, acc[r][c]);
-        }
+          for (int c = 0; c < CT; ++c) acc[r][c] = mfma_step<TE>(af, bf[c], s, acc[r][c]);
       }
     }
     buf ^= 1;
@@ -251,16 +250,14 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchArgs<TE> a) {
   typename M::Acc* out = a.out + (int64_t)split_id * a.out_split_stride;
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
-    if (r < rt_act) {
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int64_t col = col_base + c * 16 + c16;
-        if (col < a.n) {
+    for (int c = 0; c < CT; ++c) {
+      const int64_t col = col_base + c * 16 + c16;
+      if (col < a.n) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = row_base + r * 16 + M::out_row(q, i);
-            if (row < a.l) out[row + col * a.ldo] = acc[r][c][i];
-          }
+        for (int i = 0; i < 4; ++i) {
+          const int row = row_base + r * 16 + M::out_row(q, i);
+          if (row < a.l) out[row + col * a.ldo] = acc[r][c][i];
         }
       }
     }
@@ -299,13 +296,13 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(SketchArgs<TE> a) {
   const int strip = (int)(rest % ncolstrips);
   const int lchunk = (int)(rest / ncolstrips);
   const int row_base = lchunk * ROWS;
-  const int rt_act = min(RT, (a.l - row_base + 15) / 16);
   const int64_t kbeg = (int64_t)split_id * a.kchunk;
   const int64_t kend = min(a.m, kbeg + a.kchunk);
   const int nst = (int)((kend - kbeg) / BK);
   const int64_t col_base = (int64_t)strip * (4 * CT * 16) + wid * (CT * 16);
 
-  // per-thread Omega vector slots: (row, k-offset) and validity
+  // per-thread Omega vector slots: (row, k-offset) and validity (rows past
+  // l are staged as zeros)
   const TE* optr[NV];
   int lofs[NV];
   bool oval[NV];
@@ -365,14 +362,12 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(SketchArgs<TE> a) {
     for (int sub = 0; sub < SUB; ++sub) {
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        if (r < rt_act) {
-          Frag<TE> af;
-          load_frag(af, &lds[(r * 16 + c16) * LROW + sub * 4 * VEC + q * VEC]);
+        Frag<TE> af;
+        load_frag(af, &lds[(r * 16 + c16) * LROW + sub * 4 * VEC + q * VEC]);
 #pragma unroll
-          for (int s = 0; s < VEC / M::KMFMA; ++s)
+        for (int s = 0; s < VEC / M::KMFMA; ++s)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) acc[r][c] = mfma_step<TE>(af, cur[sub][c], s, acc[r][c]);
-        }
+          for (int c = 0; c < CT; ++c) acc[r][c] = mfma_step<TE>(af, cur[sub][c], s, acc[r][c]);
       }
     }
   }
@@ -380,17 +375,234 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(SketchArgs<TE> a) {
   typename M::Acc* out = a.out + (int64_t)split_id * a.out_split_stride;
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
-    if (r < rt_act) {
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int64_t col = col_base + c * 16 + c16;
-        if (cval[c]) {
+    for (int c = 0; c < CT; ++c) {
+      const int64_t col = col_base + c * 16 + c16;
+      if (cval[c]) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = row_base + r * 16 + M::out_row(q, i);
-            if (row < a.l) out[row + col * a.ldo] = acc[r][c][i];
-          }
+        for (int i = 0; i < 4; ++i) {
+          const int row = row_base + r * 16 + M::out_row(q, i);
+          if (row < a.l) out[row + col * a.ldo] = acc[r][c][i];
         }
+      }
+    }
+  }
+}
+
+// Streaming kernel (gfx950): the k-slot permutation of the kernels above,
+// with the operand traffic arranged for the hardware.
+//  * Workgroup tile: 32 RTW rows x 32 CTW columns of X, one K-range.  The
+//    four waves form a 2 x 2 grid; each multiplies RTW row tiles by CTW
+//    column tiles (16 x 16 each), so an operand fragment read from LDS feeds
+//    CTW (Omega) or RTW (A) MFMAs.
+//  * A stage is 128 bytes of K per row of Omega and per column of A (64
+//    BF16, 128 FP8 or 32 FP32 values).
+//  * Both operands go from global memory straight into LDS: buffer loads
+//    with the LDS bit, 16 bytes per lane, 32-bit offsets from a wave-uniform
+//    descriptor, no registers.  A direct load fills 8 rows (columns of A) of
+//    a stage, lane -> (row + lane / 8, slot lane % 8); within a row the
+//    16-byte slots are XOR-swizzled by (row & 7), so the MFMA operand reads
+//    (16 rows at one logical slot) spread over the LDS banks.
+//  * The Omega descriptor's range is its l rows (rows past l read as zeros);
+//    A columns past n are clamped to column 0 (their outputs are dropped).
+//  * Three stage slots rotate; the loads of stage s+2 are issued while stage
+//    s multiplies, a few at a time between its MFMAs, so HBM streams during
+//    the MFMAs.  The slot refilled at stage s was read at stage s-1, which
+//    the barrier at the top of stage s retires.  Each slot is its own LDS
+//    object, so the compiler can see that a direct load into one does not
+//    feed the reads of another, and one explicit wait per stage (the loads of
+//    stage s done, those of s+1 still in flight) hands the stage over.
+//  * Stages past the K-range (at most two, to fill the last rotation) use
+//    empty descriptors: they load zeros, touch no memory and add nothing.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// raw buffer descriptor word 3 for gfx9-family loads (32-bit data format)
+constexpr int BUF_WORD3 = 0x00020000;
+
+template <typename TE, int RTW, int CTW>
+__global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a) {
+  using M = MT<TE>;
+  using AccV = typename M::AccV;
+  using Acc = typename M::Acc;
+  constexpr int VEC = M::VEC;
+  constexpr int VB = VEC * (int)sizeof(TE);   // bytes of one lane operand
+  constexpr int NP = VB / 16;                 // 16-byte pieces per operand
+  constexpr int SB = 128;                     // stage bytes per row (8 slots)
+  constexpr int BKS = SB / (int)sizeof(TE);   // K per stage
+  constexpr int SUB = SB / (4 * VB);          // operand k-steps per stage
+  constexpr int OROWS = 32 * RTW;             // Omega rows of the workgroup
+  constexpr int ACOLS = 32 * CTW;             // A columns of the workgroup
+  constexpr int NIO = OROWS / 32;             // Omega direct loads per wave per stage
+  constexpr int NIA = ACOLS / 32;             // A direct loads per wave per stage
+  constexpr int NI = NIO + NIA;
+  constexpr int OBYTES = OROWS * SB, ABYTES = ACOLS * SB;
+  constexpr int KMF = VEC / M::KMFMA;         // MFMAs per operand pair
+  constexpr int IPS = (NI + SUB - 1) / SUB;   // direct loads slotted into each k-step
+  static_assert(SUB >= 1 && 4 * VB * SUB == SB, "stage must hold whole operand k-steps");
+  static_assert(NI <= 63, "vmcnt immediate of the hand-over");
+
+  __shared__ __attribute__((aligned(1024))) char o0[OBYTES];
+  __shared__ __attribute__((aligned(1024))) char o1[OBYTES];
+  __shared__ __attribute__((aligned(1024))) char o2[OBYTES];
+  __shared__ __attribute__((aligned(1024))) char b0[ABYTES];
+  __shared__ __attribute__((aligned(1024))) char b1[ABYTES];
+  __shared__ __attribute__((aligned(1024))) char b2[ABYTES];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wr = wid & 1, wc = wid >> 1;  // this wave's row half and column half
+  const int q = lane >> 4;
+  const int c16 = lane & 15;
+  const int bid = blockIdx.x;
+  const int split_id = bid % a.split;
+  const int rest = bid / a.split;
+  const int64_t ncolstrips = (a.n + ACOLS - 1) / ACOLS;
+  const int strip = (int)(rest % ncolstrips);
+  const int lchunk = (int)(rest / ncolstrips);
+  const int row_base = lchunk * OROWS;
+  // K-range of this split: an even share of the stages
+  const int64_t s0 = (int64_t)split_id * a.kpairs / a.split;
+  const int64_t s1 = (int64_t)(split_id + 1) * a.kpairs / a.split;
+  const int64_t kbeg = s0 * BKS;
+  const int nst = (int)(s1 - s0);
+  const int64_t col0 = (int64_t)strip * ACOLS;
+
+  // direct-load lane offsets: row (column) 8 (w + 4 i) + lane / 8 of the
+  // stage, slot (lane % 8) ^ (row & 7)
+  const int swz_st = (lane & 7) ^ (lane >> 3);
+  const char* obase = reinterpret_cast<const char*>(a.Pt + kbeg);
+  const uint32_t orange = (uint32_t)((int64_t)a.l * a.ldp * (int64_t)sizeof(TE));
+  const uint32_t orow = (uint32_t)(a.ldp * (int64_t)sizeof(TE));
+  const uint32_t ooff0 = (uint32_t)(row_base + 8 * wid + (lane >> 3)) * orow + (uint32_t)(swz_st * 16);
+  const char* abase = reinterpret_cast<const char*>(a.A + kbeg);
+  const uint32_t arange = (uint32_t)(a.n * a.lda * (int64_t)sizeof(TE));
+  const uint32_t acol = (uint32_t)(a.lda * (int64_t)sizeof(TE));
+  uint32_t aoffs[NIA];
+#pragma unroll
+  for (int i = 0; i < NIA; ++i) {
+    int64_t col = col0 + 8 * (wid + 4 * i) + (lane >> 3);
+    if (col >= a.n) col = 0;
+    aoffs[i] = (uint32_t)col * acol + (uint32_t)(swz_st * 16);
+  }
+
+  AccV acc[RTW][CTW];
+#pragma unroll
+  for (int r = 0; r < RTW; ++r)
+#pragma unroll
+    for (int c = 0; c < CTW; ++c) acc[r][c] = AccV{};
+
+  // descriptors of stage st (empty past the K-range)
+  auto orsrc = [&](int st) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(obase + (int64_t)st * SB), (short)0,
+                                             st < nst ? (int)orange : 0, BUF_WORD3);
+  };
+  auto arsrc = [&](int st) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(abase + (int64_t)st * SB), (short)0,
+                                             st < nst ? (int)arange : 0, BUF_WORD3);
+  };
+  // direct load j (0 .. NI-1) of a stage: Omega loads first, then A
+  auto dma = [&](__amdgpu_buffer_rsrc_t ors, __amdgpu_buffer_rsrc_t ars, char* ob, char* ab, int j) {
+    if (j < NIO)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ors, (lds_void_t*)(ob + 8 * (wid + 4 * j) * SB), 16,
+                                               (int)(ooff0 + (uint32_t)(32 * j) * orow), 0, 0, 0);
+    else
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, (lds_void_t*)(ab + 8 * (wid + 4 * (j - NIO)) * SB),
+                                               16, (int)aoffs[j - NIO], 0, 0, 0);
+  };
+  auto load_stage = [&](int st, char* ob, char* ab) {
+    const auto ors = orsrc(st);
+    const auto ars = arsrc(st);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) dma(ors, ars, ob, ab, j);
+  };
+
+  // operand reads: row (column) c16 of a 16-row tile; logical slot of (sub,
+  // piece p) = sub*4*NP + q*NP + p, stored at slot ^ (c16 & 7)
+  const int o_rd = (wr * RTW * 16 + c16) * SB;
+  const int a_rd = (wc * CTW * 16 + c16) * SB;
+  const int swz = c16 & 7;
+  // Stage st: MFMAs from (ob, ab); the loads of stage st + 2 go to (nob, nab),
+  // spread over the k-steps.
+  auto stage = [&](int st, const char* ob, const char* ab, char* nob, char* nab) {
+    const auto ors = orsrc(st + 2);
+    const auto ars = arsrc(st + 2);
+#pragma unroll
+    for (int sub = 0; sub < SUB; ++sub) {
+      Frag<TE> af[RTW], bf[CTW];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int slot = (sub * 4 * NP + q * NP + p) ^ swz;
+#pragma unroll
+        for (int c = 0; c < CTW; ++c)
+          reinterpret_cast<uint4*>(bf[c].v)[p] =
+              *reinterpret_cast<const uint4*>(ab + a_rd + c * 16 * SB + slot * 16);
+#pragma unroll
+        for (int r = 0; r < RTW; ++r)
+          reinterpret_cast<uint4*>(af[r].v)[p] =
+              *reinterpret_cast<const uint4*>(ob + o_rd + r * 16 * SB + slot * 16);
+      }
+#pragma unroll
+      for (int j = 0; j < IPS; ++j)
+        if (sub * IPS + j < NI) dma(ors, ars, nob, nab, sub * IPS + j);
+#pragma unroll
+      for (int r = 0; r < RTW; ++r)
+#pragma unroll
+        for (int s = 0; s < KMF; ++s)
+#pragma unroll
+          for (int c = 0; c < CTW; ++c) acc[r][c] = mfma_step<TE>(af[r], bf[c], s, acc[r][c]);
+      // issue order: this k-step's LDS reads, then its MFMAs with the loads
+      // of stage st + 2 slotted in between
+      constexpr int NM = RTW * CTW * KMF;
+      constexpr int GAP = NM / (IPS + 1) > 0 ? NM / (IPS + 1) : 1;
+      __builtin_amdgcn_sched_group_barrier(0x100, (RTW + CTW) * NP, 0);
+#pragma unroll
+      for (int v = 0; v < IPS; ++v) {
+        __builtin_amdgcn_sched_group_barrier(0x008, GAP, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, NM - IPS * GAP, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  // Stage hand-over: this wave's direct loads of stage st are done (those of
+  // st+1, NI of them, may still be in flight), then a barrier.  This is not
+  // __syncthreads(): its workgroup fence would also wait for the loads of
+  // st+1.  The statement loads nothing; its memory clobber keeps the
+  // compiler from moving LDS accesses across it.
+  auto handover = [&]() { asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(NI) : "memory"); };
+  load_stage(0, o0, b0);
+  load_stage(1, o1, b1);
+  for (int st = 0; st < nst; st += 3) {
+    handover();
+    stage(st, o0, b0, o2, b2);
+    handover();
+    stage(st + 1, o1, b1, o0, b0);
+    handover();
+    stage(st + 2, o2, b2, o1, b1);
+  }
+  // drain the direct loads of the stages past the end (empty descriptors)
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+
+  // Write the tile (X or this split's partial): lane (c16, q) holds rows
+  // 16 t + 4 q .. +4 of column c16 of tile (t, c), 4 consecutive values of
+  // one column.
+  Acc* out = a.out + (int64_t)split_id * a.out_split_stride;
+#pragma unroll
+  for (int r = 0; r < RTW; ++r) {
+#pragma unroll
+    for (int c = 0; c < CTW; ++c) {
+      const int64_t col = col0 + (wc * CTW + c) * 16 + c16;
+      const int row = row_base + (wr * RTW + r) * 16 + 4 * q;
+      if (col >= a.n || row >= a.l) continue;
+      Acc* p = out + row + col * a.ldo;
+      if (a.vec_out && row + 3 < a.l) {
+        *reinterpret_cast<AccV*>(p) = acc[r][c];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (row + i < a.l) p[i] = acc[r][c][i];
       }
     }
   }
@@ -410,16 +622,154 @@ __global__ void split_reduce_kernel(const TA* part, int split, int64_t stride, i
   }
 }
 
+// One launch with RT row tiles per l-chunk; the fast kernel needs aligned
+// operands and whole BK stages in every K-range.
+template <typename TE, int RT>
+static void launch_rt(rpid_ctx ctx, const SketchArgs<TE>& a, int64_t grid, bool aligned, bool fast) {
+  if (fast)
+    hipLaunchKernelGGL((sketch_fast_kernel<TE, RT>), dim3((unsigned)grid), dim3(256), 0, ctx->stream,
+                       a);
+  else if (aligned)
+    hipLaunchKernelGGL((sketch_kernel<TE, RT, true>), dim3((unsigned)grid), dim3(256), 0,
+                       ctx->stream, a);
+  else
+    hipLaunchKernelGGL((sketch_kernel<TE, RT, false>), dim3((unsigned)grid), dim3(256), 0,
+                       ctx->stream, a);
+}
+
+// Row tiles are a compile-time count (the MFMA loop is then straight-line
+// code that the compiler can software-pipeline); a chunk of `need` tiles runs
+// the smallest instantiated count >= need, with the extra rows discarded.
+template <typename TE>
+static int rows_per_chunk(int need) {
+  static constexpr int counts[] = {1, 2, 3, 4, 5, 6, 8, 10, 13, 17};
+  for (int c : counts)
+    if (need <= c) return c;
+  return 0;
+}
+
+template <typename TE>
+static void launch_sketch(rpid_ctx ctx, const SketchArgs<TE>& a, int64_t grid, bool aligned,
+                          bool fast, int rt) {
+  switch (rt) {
+    case 1: launch_rt<TE, 1>(ctx, a, grid, aligned, fast); break;
+    case 2: launch_rt<TE, 2>(ctx, a, grid, aligned, fast); break;
+    case 3: launch_rt<TE, 3>(ctx, a, grid, aligned, fast); break;
+    case 4: launch_rt<TE, 4>(ctx, a, grid, aligned, fast); break;
+    case 5: launch_rt<TE, 5>(ctx, a, grid, aligned, fast); break;
+    case 6: launch_rt<TE, 6>(ctx, a, grid, aligned, fast); break;
+    case 8: launch_rt<TE, 8>(ctx, a, grid, aligned, fast); break;
+    case 10: launch_rt<TE, 10>(ctx, a, grid, aligned, fast); break;
+    case 13: launch_rt<TE, 13>(ctx, a, grid, aligned, fast); break;
+    default: launch_rt<TE, 17>(ctx, a, grid, aligned, fast); break;
+  }
+}
+
+template <typename TE, int CTW>
+static void launch_stream(rpid_ctx ctx, const SketchArgs<TE>& a, int64_t grid, int rtw) {
+  switch (rtw) {
+#define RPID_STREAM_RTW(R)                                                                  \
+  case R:                                                                                  \
+    hipLaunchKernelGGL((sketch_stream_kernel<TE, R, CTW>), dim3((unsigned)grid), dim3(256), 0, \
+                       ctx->stream, a);                                                    \
+    break;
+    RPID_STREAM_RTW(1)
+    RPID_STREAM_RTW(2)
+    RPID_STREAM_RTW(3)
+    RPID_STREAM_RTW(4)
+    RPID_STREAM_RTW(5)
+    RPID_STREAM_RTW(6)
+    RPID_STREAM_RTW(7)
+    RPID_STREAM_RTW(8)
+    default:
+      RPID_STREAM_RTW(9)
+#undef RPID_STREAM_RTW
+  }
+}
+
+// Column tiles per wave of the streaming kernel, per element type.
+template <typename TE>
+struct StreamCTW {
+  static constexpr int value = 4;
+};
+
+// The streaming kernel (BF16, FP8, FP32 operands): aligned operands, K a
+// whole number of 128-byte stages, 32-bit operand offsets.  Returns false if
+// it does not apply.
+template <typename TE>
+static bool sketch_stream(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int64_t lda,
+                          int64_t m, int64_t n, int64_t l, typename MT<TE>::Acc* X, int64_t ldx,
+                          size_t ws_off, int* err) {
+  using Acc = typename MT<TE>::Acc;
+  constexpr int CTW = StreamCTW<TE>::value;
+  constexpr int BKS = 128 / (int)sizeof(TE);
+  constexpr int RTWMAX = 9;  // up to 288 rows per l-chunk
+  const int64_t sz = (int64_t)sizeof(TE);
+  const bool aligned = ((uintptr_t)A % 16 == 0) && ((uintptr_t)Pt % 16 == 0) && (lda * sz) % 16 == 0 &&
+                       (ldp * sz) % 16 == 0;
+  if (!aligned || m % BKS != 0) return false;
+  if (n * lda * sz >= ((int64_t)1 << 31) || l * ldp * sz >= ((int64_t)1 << 31)) return false;
+  // l-chunks of at most 2 RTWMAX row tiles, as even as the tile count allows
+  const int ltiles = (int)((l + 15) / 16);
+  const int lchunks = (ltiles + 2 * RTWMAX - 1) / (2 * RTWMAX);
+  const int rtw = ((ltiles + lchunks - 1) / lchunks + 1) / 2;
+  const int64_t strips = (n + 32 * CTW - 1) / (32 * CTW);
+  const int64_t kst = m / BKS;  // stages
+  int64_t split = (int64_t)ctx->num_cu / (strips * lchunks);
+  if (split > kst) split = kst;
+  if (split > 16) split = 16;
+  if (split < 1) split = 1;
+  SketchArgs<TE> a{};
+  a.Pt = Pt;
+  a.ldp = ldp;
+  a.A = A;
+  a.lda = lda;
+  a.m = m;
+  a.n = n;
+  a.l = (int)l;
+  a.split = (int)split;
+  a.kchunk = 0;
+  a.ltiles = ltiles;
+  a.kpairs = kst;
+  if (split == 1) {
+    a.out = X;
+    a.ldo = ldx;
+    a.out_split_stride = 0;
+    a.vec_out = ((uintptr_t)X % 16 == 0) && (ldx % 4 == 0);
+  } else {
+    Carve cv;
+    cv.off = ws_off;
+    size_t o_part = cv.take<Acc>((size_t)split * l * n);
+    *err = ws_check(ctx, cv.off);
+    if (*err != RPID_OK) return true;
+    a.out = ws_ptr<Acc>(ctx, o_part);
+    a.ldo = l;
+    a.out_split_stride = l * n;
+    a.vec_out = (l % 4 == 0);
+  }
+  launch_stream<TE, CTW>(ctx, a, split * strips * lchunks, rtw);
+  *err = hipGetLastError() == hipSuccess ? RPID_OK : RPID_ERR_HIP;
+  if (*err == RPID_OK && split > 1) {
+    int64_t blocks = (l * n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((split_reduce_kernel<Acc, Acc>), dim3((unsigned)blocks), dim3(256), 0,
+                       ctx->stream, a.out, (int)split, l * n, l, n, l, X, ldx);
+    *err = hipGetLastError() == hipSuccess ? RPID_OK : RPID_ERR_HIP;
+  }
+  return true;
+}
+
 template <typename TE>
 static int sketch_impl(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int64_t lda,
                        int64_t m, int64_t n, int64_t l, typename MT<TE>::Acc* X, int64_t ldx,
                        size_t ws_off) {
   using M = MT<TE>;
   using Acc = typename M::Acc;
-  constexpr int RT = 17;  // up to 272 rows per l-chunk
+  constexpr int RTMAX = 17;  // up to 272 rows per l-chunk
   if (l < 1 || l > 1024 || m < 1 || n < 1) return RPID_ERR_UNSUPPORTED;
-  const int lchunks = (int)((l + 16 * RT - 1) / (16 * RT));
   const int ltiles = (int)((l + 15) / 16);
+  const int lchunks = (ltiles + RTMAX - 1) / RTMAX;
+  const int rt = rows_per_chunk<TE>((ltiles + lchunks - 1) / lchunks);
   const int64_t colw = 4 * M::CT * 16;
   const int64_t strips = (n + colw - 1) / colw;
   // Split K so that the grid fills the chip in one round (one workgroup per
@@ -462,15 +812,7 @@ static int sketch_impl(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int
     a.out_split_stride = l * n;
   }
   const int64_t grid = split * strips * lchunks;
-  if (aligned && m % M::BK == 0)
-    hipLaunchKernelGGL((sketch_fast_kernel<TE, RT>), dim3((unsigned)grid), dim3(256), 0,
-                       ctx->stream, a);
-  else if (aligned)
-    hipLaunchKernelGGL((sketch_kernel<TE, RT, true>), dim3((unsigned)grid), dim3(256), 0,
-                       ctx->stream, a);
-  else
-    hipLaunchKernelGGL((sketch_kernel<TE, RT, false>), dim3((unsigned)grid), dim3(256), 0,
-                       ctx->stream, a);
+  launch_sketch<TE>(ctx, a, grid, aligned, aligned && m % M::BK == 0, rt);
   RPID_HIP_CHECK(hipGetLastError());
   if (split > 1) {
     int64_t blocks = (l * n + 255) / 256;
@@ -494,14 +836,24 @@ int sketch_f64(rpid_ctx ctx, const double* Pt, int64_t ldp, const double* A, int
 }
 int sketch_f32(rpid_ctx ctx, const float* Pt, int64_t ldp, const float* A, int64_t lda,
                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+  int err = RPID_OK;
+  if (l >= 1 && l <= 1024 && sketch_stream<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err))
+    return err;
   return sketch_impl<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
 }
 int sketch_e4m3(rpid_ctx ctx, const uint8_t* Pt, int64_t ldp, const uint8_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+  int err = RPID_OK;
+  if (l >= 1 && l <= 1024 && sketch_stream<uint8_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err))
+    return err;
   return sketch_impl<uint8_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
 }
 int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+  int err = RPID_OK;
+  if (l >= 1 && l <= 1024 &&
+      sketch_stream<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err))
+    return err;
   return sketch_impl<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
 }
 

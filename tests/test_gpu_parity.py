@@ -167,6 +167,27 @@ def test_sketch_f32_bf16(R, ctx, m, n, l, seed):
         assert np.all(np.abs(X - ref) <= bound), dt
 
 
+@pytest.mark.parametrize("m,n,l,seed", [(2048, 1000, 272, 6), (8192, 515, 300, 7), (1024, 130, 5, 8),
+                                        (4096, 2048, 544, 9), (256, 64, 16, 10), (16384, 200, 400, 11)])
+def test_sketch_stream_kernel(R, ctx, m, n, l, seed):
+    """Sizes that take the streaming kernel (K a whole number of 256-byte
+    stage pairs): row tiles of 1, 10, 13 and 17 with rows past l, ragged
+    column strips, one and several K-ranges, two l-chunks.  FP32 and BF16
+    against the FP64 product of the stored values, within the FP32
+    accumulation bound."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n))
+    Om = rng.standard_normal((l, m))
+    for dt in (torch.float32, torch.bfloat16):
+        say("sketch stream", dt, m, n, l)
+        Ad, Od = dev(A, dt), dev(Om, dt)
+        X = host(R.rpid_sketch(ctx, Ad, Od))
+        a_s, o_s = host(Ad), host(Od)
+        ref = O.sketch(a_s, o_s)
+        bound = 2 * m * 2.0**-24 * (np.abs(o_s) @ np.abs(a_s))
+        assert np.all(np.abs(X - ref) <= bound), dt
+
+
 # ---------------------------------------------------------------------------
 # The whole path in FP64 on the 1000 x 800 exponential-spectrum workload
 # ---------------------------------------------------------------------------
