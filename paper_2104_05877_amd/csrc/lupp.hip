@@ -33,6 +33,10 @@
 namespace rpid {
 
 static constexpr unsigned kSpinLimit = 1u << 21;  // ~2 s of polling at ~1 us per load
+// Every workgroup writes its candidate value into kValRep copies (64 KB
+// apart) and reads copy g % kValRep, so the polls of the whole grid are
+// spread over several memory channels instead of one region.
+static constexpr int kValRep = 8;
 
 template <typename T>
 struct LuppArgs {
@@ -47,7 +51,8 @@ struct LuppArgs {
   T* Uf;
   int64_t ldu;
   T* diag;
-  uint64_t* xval;   // [2][G][W] tagged candidate values
+  uint64_t* xval;   // [kValRep][2][G][W] tagged candidate values (replica stride xrep words)
+  int64_t xrep;
   uint64_t* xrow;   // [2][G][kpad][W] tagged candidate rows
   uint64_t* xflag;  // [0] abort (tag = epoch)
   unsigned epoch;   // 1 .. 2^21 - 1
@@ -205,6 +210,7 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
     cand_abs[h] = av[0];
     cand_row[h] = h * R + iv[0];
     cand_val[h] = sv[0];
+    return sv[0];
   };
   for (int q = tid; q < RW; q += nt) alive[q] = (row0 + q < a.n) ? 1 : 0;
   if (j == 0) {
@@ -243,8 +249,11 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
 
     // ---- (2) publish: candidate value, then the candidate row (tagged
     //      words; the value goes first so that it does not queue behind the
-    //      row's stores) ------------------------------------------------------
-    if (tid == 0) put_value(&a.xval[((size_t)par * G + g) * W], best, tag);
+    //      row's stores).  With one thread per column the value of steps
+    //      t > 0 went out already, from the owner of column t at the end of
+    //      step t-1. ------------------------------------------------------------
+    if (tid < kValRep && (H > 1 || t == 0))
+      put_value(&a.xval[tid * a.xrep + ((int64_t)par * G + g) * W], best, tag);
     uint64_t* myrow = a.xrow + ((size_t)par * G + g) * a.kpad * W;
     T myv = T(0);  // this thread's column of the candidate row
     const int hb = bq / R, qb = bq - hb * R;
@@ -285,7 +294,7 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
         const uint64_t* xw[PMAX];
 #pragma unroll
         for (int c = 0; c < PMAX; ++c)
-          xw[c] = &a.xval[((size_t)par * G + min(lane + 64 * c, G - 1)) * W];
+          xw[c] = &a.xval[(g % kValRep) * a.xrep + ((int64_t)par * G + min(lane + 64 * c, G - 1)) * W];
         auto request = [&](uint64_t(&w)[W * PMAX]) {
 #pragma unroll
           for (int c = 0; c < PMAX; ++c)
@@ -333,7 +342,8 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       } else {
         for (int i = lane; i < G && ok; i += 64) {
           T v;
-          ok = wait_value(&a.xval[((size_t)par * G + i) * W], tag, v, a.xflag, a.epoch);
+          ok = wait_value(&a.xval[(g % kValRep) * a.xrep + ((int64_t)par * G + i) * W], tag, v,
+                          a.xflag, a.epoch);
           if (ok) consider(i, v);
         }
       }
@@ -418,7 +428,17 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
       if (j == t + 1) {
 #pragma unroll
         for (int q = 0; q < R; ++q) colbuf[h * R + q] = s[q];
-        local_candidate();
+        const T nv = local_candidate();
+        if (H == 1 && t + 1 < k) {
+          // the workgroup's candidate of step t+1 is this thread's: publish
+          // it now rather than after the barrier (its slot was last read in
+          // step t-1, which every workgroup has finished polling by the time
+          // any workgroup has seen all values of step t)
+          const int64_t at = ((int64_t)((t + 1) & 1) * G + g) * W;
+          const unsigned tag1 = step_tag(a.epoch, t + 1);
+#pragma unroll
+          for (int r = 0; r < kValRep; ++r) put_value(&a.xval[r * a.xrep + at], nv, tag1);
+        }
       }
     }
     __syncthreads();
@@ -537,7 +557,9 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   (void)ws_off;
   constexpr int W = Words<T>::W;
   Carve cv;
-  const size_t o_val = cv.take<uint64_t>((size_t)2 * G * W);
+  // value copies 64 KB apart (or further, for large grids)
+  const int64_t xrep = ((int64_t)2 * G * W + 8191) / 8192 * 8192;
+  const size_t o_val = cv.take<uint64_t>((size_t)kValRep * xrep);
   const size_t o_row = cv.take<uint64_t>((size_t)2 * G * xstride * W);
   const size_t o_flag = cv.take<uint64_t>(1);
   bool fresh = false;
@@ -573,6 +595,7 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   a.ldu = ldu;
   a.diag = diag;
   a.xval = reinterpret_cast<uint64_t*>(ucb + o_val);
+  a.xrep = xrep;
   a.xrow = reinterpret_cast<uint64_t*>(ucb + o_row);
   a.xflag = reinterpret_cast<uint64_t*>(ucb + o_flag);
   a.epoch = ctx->lupp_epoch;
