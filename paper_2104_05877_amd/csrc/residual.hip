@@ -311,6 +311,14 @@ int residual_f64(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const TA* A, int
 int residual_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* A, int64_t lda,
                   const uint16_t* Pt, int64_t ldpt, const uint16_t* Q, int64_t ldq,
                   double* partials, double* out2) {
+  int64_t count = 0;
+  int err = RPID_OK;
+  if (residual_stream_bf16(ctx, m, n, r, A, lda, Pt, ldpt, Q, ldq, partials, &count, &err)) {
+    RPID_CHECK(err);
+    hipLaunchKernelGGL(partial_sum_kernel, dim3(1), dim3(1024), 0, ctx->stream, partials, count, out2);
+    RPID_HIP_CHECK(hipGetLastError());
+    return RPID_OK;
+  }
   dim3 grid((unsigned)((m + 127) / 128), (unsigned)((n + 127) / 128));
   hipLaunchKernelGGL(residual_bf16_kernel, grid, dim3(256), 0, ctx->stream, m, n, r, A, lda, Pt,
                      ldpt, Q, ldq, partials);

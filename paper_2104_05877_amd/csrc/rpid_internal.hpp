@@ -118,6 +118,9 @@ int sketch_e4m3(rpid_ctx ctx, const uint8_t* Pt, int64_t ldp, const uint8_t* A, 
 int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
 size_t sketch_workspace_bytes(rpid_ctx ctx, int64_t m, int64_t n, int64_t l, int elem_acc);
+bool residual_stream_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* R,
+                          int64_t ldr, const uint16_t* Pt, int64_t ldpt, const uint16_t* Q,
+                          int64_t ldq, double* partials, int64_t* count, int* err);
 
 // General FP64 GEMM: C = alpha op(A) op(B) + beta C, column-major.
 int dgemm(rpid_ctx ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t K, double alpha,

@@ -146,6 +146,11 @@ struct SketchArgs {
   int64_t out_split_stride;   // elements between split slices (0 if split == 1)
   int64_t kpairs;             // streaming kernel: K in stages, shared out evenly
   int vec_out;                // streaming kernel: out rows writable as 4-element vectors
+  // residual epilogue: R (l x n, BF16) minus the product, squared and summed
+  const uint16_t* R;
+  int64_t ldr;
+  int vec_r;                  // 4 consecutive rows of R are one 8-byte load
+  double* partials;           // [grid][2]: sum (R - product)^2, sum R^2
 };
 
 template <typename TE, int RT, bool ALIGNED>
@@ -419,7 +424,7 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // raw buffer descriptor word 3 for gfx9-family loads (32-bit data format)
 constexpr int BUF_WORD3 = 0x00020000;
 
-template <typename TE, int RTW, int CTW>
+template <typename TE, int RTW, int CTW, bool RESID>
 __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a) {
   using M = MT<TE>;
   using AccV = typename M::AccV;
@@ -585,24 +590,71 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
   // drain the direct loads of the stages past the end (empty descriptors)
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
-  // Write the tile (X or this split's partial): lane (c16, q) holds rows
-  // 16 t + 4 q .. +4 of column c16 of tile (t, c), 4 consecutive values of
-  // one column.
-  Acc* out = a.out + (int64_t)split_id * a.out_split_stride;
+  if constexpr (RESID) {
+    // ||R - product||^2 and ||R||^2 over this tile, in FP64; lane (c16, q)
+    // holds rows 16 t + 4 q .. +4 of column c16 of tile (t, c)
+    double sd = 0.0, sa = 0.0;
 #pragma unroll
-  for (int r = 0; r < RTW; ++r) {
+    for (int r = 0; r < RTW; ++r) {
 #pragma unroll
-    for (int c = 0; c < CTW; ++c) {
-      const int64_t col = col0 + (wc * CTW + c) * 16 + c16;
-      const int row = row_base + (wr * RTW + r) * 16 + 4 * q;
-      if (col >= a.n || row >= a.l) continue;
-      Acc* p = out + row + col * a.ldo;
-      if (a.vec_out && row + 3 < a.l) {
-        *reinterpret_cast<AccV*>(p) = acc[r][c];
-      } else {
+      for (int c = 0; c < CTW; ++c) {
+        const int64_t col = col0 + (wc * CTW + c) * 16 + c16;
+        const int row = row_base + (wr * RTW + r) * 16 + 4 * q;
+        if (col >= a.n || row >= a.l) continue;
+        const uint16_t* p = a.R + row + col * a.ldr;
+        uint16_t rb[4];
+        if (a.vec_r && row + 3 < a.l) {
+          const uint2 v = *reinterpret_cast<const uint2*>(p);
+          __builtin_memcpy(rb, &v, 8);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (row + i < a.l) p[i] = acc[r][c][i];
+          for (int i = 0; i < 4; ++i) rb[i] = (row + i < a.l) ? p[i] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double rv = (double)__uint_as_float((uint32_t)rb[i] << 16);
+          const double d = rv - (double)acc[r][c][i];
+          sd = fma(d, d, sd);
+          sa = fma(rv, rv, sa);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      sd += __shfl_xor(sd, off, 64);
+      sa += __shfl_xor(sa, off, 64);
+    }
+    __shared__ double red[2][4];
+    if (lane == 0) {
+      red[0][wid] = sd;
+      red[1][wid] = sa;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      a.partials[2 * (int64_t)bid] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+      a.partials[2 * (int64_t)bid + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+    return;
+  } else {
+    // Write the tile (X or this split's partial): lane (c16, q) holds rows
+    // 16 t + 4 q .. +4 of column c16 of tile (t, c), 4 consecutive values of
+    // one column.
+    Acc* out = a.out + (int64_t)split_id * a.out_split_stride;
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) {
+#pragma unroll
+      for (int c = 0; c < CTW; ++c) {
+        const int64_t col = col0 + (wc * CTW + c) * 16 + c16;
+        const int row = row_base + (wr * RTW + r) * 16 + 4 * q;
+        if (col >= a.n || row >= a.l) continue;
+        Acc* p = out + row + col * a.ldo;
+        if (a.vec_out && row + 3 < a.l) {
+          *reinterpret_cast<AccV*>(p) = acc[r][c];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (row + i < a.l) p[i] = acc[r][c][i];
+        }
       }
     }
   }
@@ -670,7 +722,7 @@ static void launch_stream(rpid_ctx ctx, const SketchArgs<TE>& a, int64_t grid, i
   switch (rtw) {
 #define RPID_STREAM_RTW(R)                                                                  \
   case R:                                                                                  \
-    hipLaunchKernelGGL((sketch_stream_kernel<TE, R, CTW>), dim3((unsigned)grid), dim3(256), 0, \
+    hipLaunchKernelGGL((sketch_stream_kernel<TE, R, CTW, false>), dim3((unsigned)grid), dim3(256), 0, \
                        ctx->stream, a);                                                    \
     break;
     RPID_STREAM_RTW(1)
@@ -756,6 +808,45 @@ static bool sketch_stream(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, 
                        ctx->stream, a.out, (int)split, l * n, l, n, l, X, ldx);
     *err = hipGetLastError() == hipSuccess ? RPID_OK : RPID_ERR_HIP;
   }
+  return true;
+}
+
+// ||R - P Q||_F^2 and ||R||_F^2 on the streaming kernel (BF16 operands, FP32
+// accumulation, FP64 epilogue): Pt is r x m and Q is r x n, both
+// k-contiguous; 128 x 128 tiles, one per workgroup, partial sums per
+// workgroup in launch order.  Returns false (nothing launched) if the shapes
+// or alignments do not suit it; otherwise *count is the number of partials.
+bool residual_stream_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* R,
+                          int64_t ldr, const uint16_t* Pt, int64_t ldpt, const uint16_t* Q,
+                          int64_t ldq, double* partials, int64_t* count, int* err) {
+  constexpr int RTW = 4, CTW = 4, BKS = 64;
+  const bool aligned = ((uintptr_t)Pt % 16 == 0) && ((uintptr_t)Q % 16 == 0) && (ldpt * 2) % 16 == 0 &&
+                       (ldq * 2) % 16 == 0;
+  if (!aligned || r % BKS != 0 || r < BKS) return false;
+  if (n * ldq * 2 >= ((int64_t)1 << 31) || m * ldpt * 2 >= ((int64_t)1 << 31)) return false;
+  const int64_t lchunks = (m + 32 * RTW - 1) / (32 * RTW);
+  const int64_t strips = (n + 32 * CTW - 1) / (32 * CTW);
+  SketchArgs<uint16_t> a{};
+  a.Pt = Pt;
+  a.ldp = ldpt;
+  a.A = Q;
+  a.lda = ldq;
+  a.m = r;
+  a.n = n;
+  a.l = (int)m;
+  a.split = 1;
+  a.kchunk = 0;
+  a.ltiles = (int)((m + 15) / 16);
+  a.kpairs = r / BKS;
+  a.R = R;
+  a.ldr = ldr;
+  a.vec_r = ((uintptr_t)R % 8 == 0) && (ldr % 4 == 0);
+  a.partials = partials;
+  const int64_t grid = lchunks * strips;
+  hipLaunchKernelGGL((sketch_stream_kernel<uint16_t, RTW, CTW, true>), dim3((unsigned)grid), dim3(256),
+                     0, ctx->stream, a);
+  *err = hipGetLastError() == hipSuccess ? RPID_OK : RPID_ERR_HIP;
+  *count = grid;
   return true;
 }
 

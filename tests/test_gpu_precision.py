@@ -152,3 +152,42 @@ def test_bf16_k512_end_to_end(R, ctx):
     ro = O.residuals(A, o["J"], Z=o["Z"], I=o["I"], U=o["U"], only=("id", "cur"))
     say("gpu", rid, rcur, "oracle", ro["id"], ro["cur"])
     assert rid <= 1.05 * ro["id"] and rcur <= 1.05 * ro["cur"]
+
+
+@pytest.mark.parametrize("m,n,k,seed", [(1000, 700, 64, 1), (2048, 1536, 128, 2), (777, 300, 192, 3),
+                                        (640, 513, 50, 4)])
+def test_bf16_residual_against_oracle(R, ctx, m, n, k, seed):
+    """BF16-storage residuals (BF16 MFMA with FP32 accumulation over the
+    three-term BF16 split of the FP64 factor) against the FP64 oracle's
+    explicit differences on the same stored values: |r_gpu - r_oracle|
+    ||A|| <= gamma || |P| |Q| ||_F with gamma = (3 k + 3) 2^-24 (FP32
+    accumulation over 3 k terms plus the split's remainder).  k = 64, 128,
+    192 take the streaming kernel (ragged 128 x 128 tiles at these m, n);
+    k = 50 the general one."""
+    say("bf16 residual", m, n, k)
+    rng = np.random.default_rng(seed)
+    A = (rng.standard_normal((m, n)) * 10.0 ** rng.uniform(-1, 1, n)[None, :])
+    Ad = inputs.torch_colmajor(A, torch.bfloat16, "cuda")
+    a_s = host(Ad)
+    J = np.sort(rng.choice(n, k, replace=False)).astype(np.int64)
+    I = np.sort(rng.choice(m, k, replace=False)).astype(np.int64)
+    C = a_s[:, J]
+    # Z and U that leave a moderate residual (a least-squares fit plus noise)
+    Z = np.linalg.lstsq(C, a_s, rcond=None)[0] + 1e-3 * rng.standard_normal((k, n))
+    Rr = a_s[I, :]
+    U = np.linalg.pinv(C) @ a_s @ np.linalg.pinv(Rr) + 1e-3 * rng.standard_normal((k, k))
+    Jd = torch.tensor(J, device="cuda")
+    Id = torch.tensor(I, device="cuda")
+    gamma = (3 * k + 3) * 2.0**-24
+    na = np.linalg.norm(a_s)
+    rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, Jd, Z=torch.tensor(Z.T.copy(), device="cuda").T)
+    ro = O.residuals(a_s, J, Z=Z, only=("id",))["id"]
+    bound = gamma * np.linalg.norm(np.abs(C) @ np.abs(Z)) / na
+    say("id", rid, ro, bound)
+    assert abs(rid - ro) <= bound + 1e-12
+    rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, k, Jd, I=Id, U=torch.tensor(U.T.copy(), device="cuda").T)
+    ro = O.residuals(a_s, J, I=I, U=U, only=("cur",))["cur"]
+    bound = gamma * np.linalg.norm(np.abs(C @ U) @ np.abs(Rr)) / na
+    say("cur", rcur, ro, bound)
+    assert abs(rcur - ro) <= bound + 1e-12
+
