@@ -9,7 +9,7 @@
 namespace rpid {
 
 namespace {
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64, TK = 32;
 
 struct GemmArgs {
   bool ta, tb;
@@ -25,18 +25,15 @@ struct GemmArgs {
   int64_t part_stride;  // 0: write C with alpha/beta; else partial slices
 };
 
-__device__ __forceinline__ double opA(const GemmArgs& a, int64_t i, int64_t k) {
-  return a.ta ? a.A[k + i * a.lda] : a.A[i + k * a.lda];
-}
-__device__ __forceinline__ double opB(const GemmArgs& a, int64_t k, int64_t j) {
-  return a.tb ? a.B[j + k * a.ldb] : a.B[k + j * a.ldb];
-}
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // 64 x 64 output tile per workgroup; 4 waves each own a 32 x 32 quadrant
-// (2 x 2 FP64 MFMA 16x16x4 tiles).  op(A) / op(B) tiles of 16 along K are
-// staged in LDS (transposes resolved while staging), one step ahead.
+// (2 x 2 FP64 MFMA 16x16x4 tiles).  op(A) / op(B) tiles of 32 along K are
+// staged in LDS (transposes resolved while staging).  The global loads run
+// two K-steps ahead in two register sets, so one K-step's MFMAs (32 per
+// wave) cover the latency of the loads of the step after next.
+template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs a) {
   __shared__ double As[TK][TM + 1];
   __shared__ double Bs[TK][TN + 1];
@@ -52,48 +49,38 @@ __global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs a) {
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = v4d{};
-  // Tile loads: each thread fetches 4 elements of op(A) and 4 of op(B) per
-  // K-step; the next step's 8 loads are issued before this step's MFMAs.
+  // Tile loads: each thread fetches PER elements of op(A) and of op(B) per
+  // K-step, along the contiguous dimension of the stored matrix: element
+  // e = tid + 256 u of the tile, (i, k) = (e % TM, e / TM) for a stored A
+  // (column-major, i contiguous) and (e / TK, e % TK) for a transposed one.
   constexpr int PER = TM * TK / 256;
-  int ai[PER], ak[PER], bj[PER], bk[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = tid + 256 * u;
-    if (a.ta) {
-      ak[u] = e % TK;
-      ai[u] = e / TK;
-    } else {
-      ai[u] = e % TM;
-      ak[u] = e / TM;
-    }
-    if (a.tb) {
-      bj[u] = e % TN;
-      bk[u] = e / TN;
-    } else {
-      bk[u] = e % TK;
-      bj[u] = e / TK;
-    }
-  }
-  double av_n[PER], bv_n[PER];
-  auto fetch = [&](int64_t k0) {
+  static_assert(256 % TM == 0 && 256 % TK == 0, "staging layout");
+  auto ai = [&](int u) { return TA ? (tid + 256 * u) / TK : (tid + 256 * u) % TM; };
+  auto ak = [&](int u) { return TA ? (tid + 256 * u) % TK : (tid + 256 * u) / TM; };
+  auto bj = [&](int u) { return TB ? (tid + 256 * u) % TN : (tid + 256 * u) / TK; };
+  auto bk = [&](int u) { return TB ? (tid + 256 * u) / TN : (tid + 256 * u) % TK; };
+  struct Regs {
+    double av[PER], bv[PER];
+  };
+  auto fetch = [&](Regs& r, int64_t k0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int64_t gi = i0 + ai[u], gk = k0 + ak[u];
-      av_n[u] = (gi < a.M && gk < ke) ? opA(a, gi, gk) : 0.0;
-      const int64_t gj = j0 + bj[u], gq = k0 + bk[u];
-      bv_n[u] = (gj < a.N && gq < ke) ? opB(a, gq, gj) : 0.0;
+      const int64_t gi = i0 + ai(u), gk = k0 + ak(u);
+      r.av[u] = (gi < a.M && gk < ke) ? (TA ? a.A[gk + gi * a.lda] : a.A[gi + gk * a.lda]) : 0.0;
+      const int64_t gj = j0 + bj(u), gq = k0 + bk(u);
+      r.bv[u] = (gj < a.N && gq < ke) ? (TB ? a.B[gj + gq * a.ldb] : a.B[gq + gj * a.ldb]) : 0.0;
     }
   };
-  if (kb < ke) fetch(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += TK) {
-    __syncthreads();
+  auto step = [&](const Regs& r) {
+    __syncthreads();  // the previous step's LDS reads are done
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      As[ak[u]][ai[u]] = av_n[u];
-      Bs[bk[u]][bj[u]] = bv_n[u];
+      As[ak(u)][ai(u)] = r.av[u];
+      Bs[bk(u)][bj(u)] = r.bv[u];
     }
     __syncthreads();
-    if (k0 + TK < ke) fetch(k0 + TK);
+  };
+  auto multiply = [&]() {
 #pragma unroll
     for (int s = 0; s < TK / 4; ++s) {
       const int kk = s * 4 + (lane >> 4);
@@ -108,6 +95,18 @@ __global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs a) {
         for (int y = 0; y < 2; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[x], qb[y], acc[x][y], 0, 0, 0);
     }
+  };
+  Regs r0, r1;
+  if (kb < ke) fetch(r0, kb);
+  if (kb + TK < ke) fetch(r1, kb + TK);
+  for (int64_t k0 = kb; k0 < ke; k0 += 2 * TK) {
+    step(r0);
+    if (k0 + 2 * TK < ke) fetch(r0, k0 + 2 * TK);
+    multiply();
+    if (k0 + TK >= ke) break;
+    step(r1);
+    if (k0 + 3 * TK < ke) fetch(r1, k0 + 3 * TK);
+    multiply();
   }
   // FP64 MFMA result: register i of lane l is row (l / 16) + 4 i, column l % 16
 #pragma unroll
@@ -142,6 +141,17 @@ __global__ void dgemm_reduce_kernel(const double* part, int splits, int64_t stri
 }
 }  // namespace
 
+static void launch_dgemm(rpid_ctx ctx, const GemmArgs& a, dim3 grid) {
+  if (a.ta && a.tb)
+    hipLaunchKernelGGL((dgemm_kernel<true, true>), grid, dim3(256), 0, ctx->stream, a);
+  else if (a.ta)
+    hipLaunchKernelGGL((dgemm_kernel<true, false>), grid, dim3(256), 0, ctx->stream, a);
+  else if (a.tb)
+    hipLaunchKernelGGL((dgemm_kernel<false, true>), grid, dim3(256), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, dim3(256), 0, ctx->stream, a);
+}
+
 int dgemm(rpid_ctx ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t K, double alpha,
           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
           int64_t ldc, size_t ws_off) {
@@ -163,9 +173,9 @@ int dgemm(rpid_ctx ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t 
   const int64_t gm = (M + TM - 1) / TM, gn = (N + TN - 1) / TN;
   int64_t splits = 1;
   const int64_t want = 2 * (int64_t)ctx->num_cu;
-  if (gm * gn < want && K > 4 * TK) {
+  if (gm * gn < want && K > 2 * TK) {
     splits = (want + gm * gn - 1) / (gm * gn);
-    const int64_t maxs = (K + 255) / 256;  // at least 256 of K per split
+    const int64_t maxs = (K + 2 * TK - 1) / (2 * TK);  // at least two K-steps per split
     if (splits > maxs) splits = maxs;
     if (splits > 64) splits = 64;
     if (splits < 1) splits = 1;
@@ -176,8 +186,7 @@ int dgemm(rpid_ctx ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t 
   if (splits < 1) splits = 1;
   if (splits == 1) {
     a.part_stride = 0;
-    hipLaunchKernelGGL(dgemm_kernel, dim3((unsigned)gm, (unsigned)gn, 1), dim3(256), 0,
-                       ctx->stream, a);
+    launch_dgemm(ctx, a, dim3((unsigned)gm, (unsigned)gn, 1));
     RPID_HIP_CHECK(hipGetLastError());
     return RPID_OK;
   }
@@ -188,8 +197,7 @@ int dgemm(rpid_ctx ctx, bool transA, bool transB, int64_t M, int64_t N, int64_t 
   double* part = ws_ptr<double>(ctx, o_part);
   a.C = part;
   a.part_stride = M * N;
-  hipLaunchKernelGGL(dgemm_kernel, dim3((unsigned)gm, (unsigned)gn, (unsigned)splits), dim3(256),
-                     0, ctx->stream, a);
+  launch_dgemm(ctx, a, dim3((unsigned)gm, (unsigned)gn, (unsigned)splits));
   RPID_HIP_CHECK(hipGetLastError());
   int64_t blocks = (M * N + 255) / 256;
   if (blocks > 4096) blocks = 4096;

@@ -497,6 +497,22 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
 #pragma unroll
     for (int c = 0; c < CTW; ++c) acc[r][c] = AccV{};
 
+  // Residual: this lane's values of R (4 consecutive rows of one column per
+  // tile) are requested now and land while the product is formed.
+  uint2 rpre[RESID ? RTW : 1][RESID ? CTW : 1];
+  if constexpr (RESID) {
+#pragma unroll
+    for (int r = 0; r < RTW; ++r)
+#pragma unroll
+      for (int c = 0; c < CTW; ++c) {
+        const int64_t col = col0 + (wc * CTW + c) * 16 + c16;
+        const int row = row_base + (wr * RTW + r) * 16 + 4 * q;
+        rpre[r][c] = make_uint2(0u, 0u);
+        if (a.vec_r && col < a.n && row + 3 < a.l)
+          rpre[r][c] = *reinterpret_cast<const uint2*>(a.R + row + col * a.ldr);
+      }
+  }
+
   // descriptors of stage st (empty past the K-range)
   auto orsrc = [&](int st) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(obase + (int64_t)st * SB), (short)0,
@@ -604,8 +620,7 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
         const uint16_t* p = a.R + row + col * a.ldr;
         uint16_t rb[4];
         if (a.vec_r && row + 3 < a.l) {
-          const uint2 v = *reinterpret_cast<const uint2*>(p);
-          __builtin_memcpy(rb, &v, 8);
+          __builtin_memcpy(rb, &rpre[r][c], 8);
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i) rb[i] = (row + i < a.l) ? p[i] : (uint16_t)0;
@@ -813,13 +828,13 @@ static bool sketch_stream(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, 
 
 // ||R - P Q||_F^2 and ||R||_F^2 on the streaming kernel (BF16 operands, FP32
 // accumulation, FP64 epilogue): Pt is r x m and Q is r x n, both
-// k-contiguous; 128 x 128 tiles, one per workgroup, partial sums per
+// k-contiguous; 256 x 128 tiles, one per workgroup, partial sums per
 // workgroup in launch order.  Returns false (nothing launched) if the shapes
 // or alignments do not suit it; otherwise *count is the number of partials.
 bool residual_stream_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* R,
                           int64_t ldr, const uint16_t* Pt, int64_t ldpt, const uint16_t* Q,
                           int64_t ldq, double* partials, int64_t* count, int* err) {
-  constexpr int RTW = 4, CTW = 4, BKS = 64;
+  constexpr int RTW = 8, CTW = 4, BKS = 64;
   const bool aligned = ((uintptr_t)Pt % 16 == 0) && ((uintptr_t)Q % 16 == 0) && (ldpt * 2) % 16 == 0 &&
                        (ldq * 2) % 16 == 0;
   if (!aligned || r % BKS != 0 || r < BKS) return false;
