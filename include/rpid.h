@@ -84,6 +84,26 @@ int rpid_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t 
                 int64_t ldx);
 
 /*
+ * Row sketch with one plain power iteration, eq. (def_power_iter) with q = 1
+ * (the Rand-LUPP-1piter variant of Sec. 5): X = Omega A^T A, formed as
+ * Y^T = Omega A^T and then X = Y^T A.  Omega here is l x n (it multiplies
+ * the columns of A).
+ *   A      m x n, lda >= m, type a_t
+ *   Omega  l x n, ldo >= l, type o_t
+ *   X      l x n, ldx >= l, type x_t (output)
+ * Supported (a_t, o_t, x_t): (F64,F64,F64), (F32,F32,F32) and
+ * (BF16,BF16,F32).  In the BF16 form Y^T is formed in FP32 and enters the
+ * second product as two BF16 terms (about 16 significant bits).
+ * 1 <= l <= 512.  Workspace: one transposed copy of A plus the Y^T factors
+ * (the context's workspace grows to about m n e_A + 4 l (m + n) bytes).
+ * Errors: -position for an invalid argument, RPID_ERR_UNSUPPORTED for other
+ * type combinations, RPID_ERR_NOMEM if the workspace cannot grow.
+ */
+int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                       int64_t lda, const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo,
+                       void* X, rpid_dtype x_t, int64_t ldx);
+
+/*
  * S2, FP8 form -- X = Omega A with A and Omega quantised to OCP E4M3 with
  * power-of-two scales, multiplied on FP8 MFMA with FP32 accumulation, and
  * the scales undone exactly in X:

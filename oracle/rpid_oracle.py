@@ -9,6 +9,8 @@ randomized pivoting algorithms for CUR and interpolative decompositions":
 
 * sketch            -- Alg. 2 (Randomized LUPP skeleton selection), step 2:
                        X = Gamma A with a Gaussian embedding Gamma (Sec. 2.2).
+* sketch_power1     -- the row sketch with one plain power iteration,
+                       eq. (def_power_iter) with q = 1: X = Omega A^T A.
 * lupp_colwise      -- column-wise LU with partial pivoting of Sec. 2.4,
                        eq. (def_LUPP), Alg. 2 step 3.
 * id_coeffs         -- ID coefficients from the pivoted sketch, Sec. 4:
@@ -71,6 +73,18 @@ def _f64(a):
 def sketch(A, Omega):
     """X = Omega A (l x n) in float64 (Alg. 2, step 2)."""
     return _f64(Omega) @ _f64(A)
+
+
+# --------------------------------------------------------------------------
+# Row sketch with one plain power iteration, eq. (def_power_iter) with q = 1
+# (the Rand-LUPP-1piter variant of Sec. 5): Omega is l x n here
+# --------------------------------------------------------------------------
+def sketch_power1(A, Omega):
+    """X = Omega (A^T A) (l x n), formed as Y = A Omega^T (m x l) and then
+    X = Y^T A, the order eq. (def_power_iter) implies for q = 1."""
+    A = _f64(A)
+    Y = A @ _f64(Omega).T
+    return Y.T @ A
 
 
 # --------------------------------------------------------------------------

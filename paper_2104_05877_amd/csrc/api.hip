@@ -463,6 +463,124 @@ int rpid_sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Sketch with one plain power iteration (eq. def_power_iter, q = 1):
+// Y^T = Omega A^T, then X = Y^T A.  Both products run on the sketch kernels,
+// whose contraction runs along the contiguous dimension of the right factor:
+// A^T is formed once (n x m), and Y^T becomes the left factor of the second
+// product.  In the BF16 form Y^T (FP32) enters the second product as two
+// BF16 terms (its rounding and the rounding of the remainder), stacked as
+// 2 l rows whose two halves are added afterwards.
+namespace {
+
+__device__ __forceinline__ uint16_t bf16_rne_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// P (m x 2l, ldp): P(i, r) = hi(Y^T(r, i)), P(i, l + r) = lo(Y^T(r, i)) with
+// hi + lo the two-term BF16 split of the FP32 value (32 x 32 LDS tiles)
+__global__ __launch_bounds__(256) void split_t_bf16_kernel(int64_t l, int64_t m, const float* Yt,
+                                                           int64_t ldy, uint16_t* P, int64_t ldp) {
+  __shared__ float tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, i0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t r = r0 + tx, i = i0 + yy;
+    tile[yy][tx] = (r < l && i < m) ? Yt[r + i * ldy] : 0.0f;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t i = i0 + tx, r = r0 + yy;
+    if (r < l && i < m) {
+      const float y = tile[tx][yy];
+      const uint16_t hi = bf16_rne_bits(y);
+      const uint16_t lo = bf16_rne_bits(y - __uint_as_float((uint32_t)hi << 16));
+      P[i + r * ldp] = hi;
+      P[i + (l + r) * ldp] = lo;
+    }
+  }
+}
+
+// X(r, j) = X2(r, j) + X2(l + r, j)
+__global__ void add_halves_f32_kernel(int64_t l, int64_t n, const float* X2, int64_t ld2, float* X,
+                                      int64_t ldx) {
+  const int64_t total = l * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % l, j = e / l;
+    X[r + j * ldx] = X2[r + j * ld2] + X2[l + r + j * ld2];
+  }
+}
+
+}  // namespace
+
+int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                       int64_t lda, const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo,
+                       void* X, rpid_dtype x_t, int64_t ldx) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (!Omega) return -7;
+  if (l < 1 || l > 512) return -9;
+  if (ldo < l) return -10;
+  if (!X) return -11;
+  if (ldx < l) return -13;
+  const bool f64 = a_t == RPID_F64 && o_t == RPID_F64 && x_t == RPID_F64;
+  const bool f32 = a_t == RPID_F32 && o_t == RPID_F32 && x_t == RPID_F32;
+  const bool bf = a_t == RPID_BF16 && o_t == RPID_BF16 && x_t == RPID_F32;
+  if (!(f64 || f32 || bf)) return RPID_ERR_UNSUPPORTED;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  const size_t es = esize(a_t);
+  const size_t acc = f64 ? 8 : 4;
+  const int64_t l2 = bf ? 2 * l : l;  // rows of the second product's left factor
+  Carve cv;
+  const size_t o_at = cv.take<char>((size_t)m * n * es);
+  const size_t o_p1 = cv.take<char>((size_t)n * l * es);
+  const size_t o_yt = cv.take<char>((size_t)l * m * acc);
+  const size_t o_p2 = cv.take<char>((size_t)m * l2 * es);
+  const size_t o_x2 = bf ? cv.take<float>((size_t)l2 * n) : 0;
+  const size_t ws_sk = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, ws_sk + std::max(sketch_workspace_bytes(ctx, n, m, l, (int)acc),
+                                                    sketch_workspace_bytes(ctx, m, n, l2, (int)acc))));
+  char* at = ws_ptr<char>(ctx, o_at);
+  char* p1 = ws_ptr<char>(ctx, o_p1);
+  char* yt = ws_ptr<char>(ctx, o_yt);
+  char* p2 = ws_ptr<char>(ctx, o_p2);
+  if (f64) {
+    RPID_CHECK(transpose_copy<double>(ctx, m, n, (const double*)A, lda, (double*)at, n));
+    RPID_CHECK(transpose_copy<double>(ctx, l, n, (const double*)Omega, ldo, (double*)p1, n));
+    RPID_CHECK(sketch_f64(ctx, (const double*)p1, n, (const double*)at, n, n, m, l, (double*)yt, l, ws_sk));
+    RPID_CHECK(transpose_copy<double>(ctx, l, m, (const double*)yt, l, (double*)p2, m));
+    return sketch_f64(ctx, (const double*)p2, m, (const double*)A, lda, m, n, l, (double*)X, ldx, ws_sk);
+  }
+  if (f32) {
+    RPID_CHECK(transpose_copy<float>(ctx, m, n, (const float*)A, lda, (float*)at, n));
+    RPID_CHECK(transpose_copy<float>(ctx, l, n, (const float*)Omega, ldo, (float*)p1, n));
+    RPID_CHECK(sketch_f32(ctx, (const float*)p1, n, (const float*)at, n, n, m, l, (float*)yt, l, ws_sk));
+    RPID_CHECK(transpose_copy<float>(ctx, l, m, (const float*)yt, l, (float*)p2, m));
+    return sketch_f32(ctx, (const float*)p2, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
+  }
+  RPID_CHECK(transpose_copy<uint16_t>(ctx, m, n, (const uint16_t*)A, lda, (uint16_t*)at, n));
+  RPID_CHECK(transpose_copy<uint16_t>(ctx, l, n, (const uint16_t*)Omega, ldo, (uint16_t*)p1, n));
+  RPID_CHECK(sketch_bf16(ctx, (const uint16_t*)p1, n, (const uint16_t*)at, n, n, m, l, (float*)yt, l, ws_sk));
+  dim3 grid((unsigned)((m + 31) / 32), (unsigned)((l + 31) / 32));
+  hipLaunchKernelGGL(split_t_bf16_kernel, grid, dim3(256), 0, ctx->stream, l, m, (const float*)yt, l,
+                     (uint16_t*)p2, m);
+  RPID_HIP_CHECK(hipGetLastError());
+  float* x2 = ws_ptr<float>(ctx, o_x2);
+  RPID_CHECK(sketch_bf16(ctx, (const uint16_t*)p2, m, (const uint16_t*)A, lda, m, n, l2, x2, l2, ws_sk));
+  int64_t blocks = (l * n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(add_halves_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, l, n, x2,
+                     l2, (float*)X, ldx);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+
+// ---------------------------------------------------------------------------
 int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
                         int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
                         int64_t ldu, void* diagU, int64_t* k_eff) {

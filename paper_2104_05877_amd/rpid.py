@@ -45,6 +45,7 @@ _SIGS = {
     "rpid_status_string": (ctypes.c_char_p, [_i]),
     "rpid_version": (_i, []),
     "rpid_sketch": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
+    "rpid_sketch_power1": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
     "rpid_sketch_fp8": (_i, [_P, _P, _I, _I, _I, _P, _I, _I, _P, _I]),
     "rpid_select_columns": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, ctypes.POINTER(_I)]),
     "rpid_id_coeffs": (
@@ -168,6 +169,22 @@ def rpid_sketch(ctx: Context, A: torch.Tensor, Omega: torch.Tensor, out_dtype=No
     s = lib().rpid_sketch(ctx.handle, pa, dtype_code(A), m, n, lda, po, dtype_code(Omega), l, ldo, px,
                           dtype_code(X), ldx)
     _check("rpid_sketch", s)
+    return X
+
+
+def rpid_sketch_power1(ctx: Context, A: torch.Tensor, Omega: torch.Tensor) -> torch.Tensor:
+    """X = Omega A^T A (one plain power iteration); Omega is l x n.  BF16
+    inputs give an FP32 X."""
+    pa, m, n, lda = colmajor(A)
+    po, l, n2, ldo = colmajor(Omega)
+    if n2 != n:
+        raise ValueError("Omega must have n columns")
+    out_dtype = torch.float32 if A.dtype == torch.bfloat16 else A.dtype
+    X = empty_colmajor(l, n, out_dtype, A.device)
+    px, _, _, ldx = colmajor(X)
+    s = lib().rpid_sketch_power1(ctx.handle, pa, dtype_code(A), m, n, lda, po, dtype_code(Omega), l, ldo,
+                                 px, dtype_code(X), ldx)
+    _check("rpid_sketch_power1", s)
     return X
 
 

@@ -318,3 +318,56 @@ ALL_PINS = [
     pin_e4m3,
     pin_sketch_fp8_exact,
 ]
+
+
+def pin_power_orthonormal(O, seed=41, m=60, n=25, l=7):
+    """eq. (def_power_iter), q = 1: with orthonormal columns (A^T A = I) the
+    power sketch is Omega itself."""
+    rng = np.random.default_rng(seed)
+    a, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    om = rng.standard_normal((l, n))
+    np.testing.assert_allclose(O.sketch_power1(a, om), om, rtol=0, atol=1e-12)
+
+
+def pin_power_diagonal(O, seed=42, n=9, l=4):
+    """A = diag(d) (small integers, exact arithmetic): X = Omega diag(d^2)."""
+    rng = np.random.default_rng(seed)
+    d = rng.integers(-5, 6, n).astype(float)
+    a = np.zeros((n + 3, n))
+    a[:n, :n] = np.diag(d)
+    om = rng.integers(-3, 4, (l, n)).astype(float)
+    assert np.array_equal(O.sketch_power1(a, om), om * (d * d)[None, :])
+
+
+def pin_power_exact_rank(O, seed=43, m=90, n=70, k=8):
+    """rank(A) = k and l = k: the power sketch spans A's row space, so the ID
+    from its LUPP pivots reproduces A (Lemma 1)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+    om = rng.standard_normal((k, n))
+    X = O.sketch_power1(a, om)
+    J = O.lupp_colwise(X, k)["J"]
+    Z = O.id_coeffs(X, J, k)
+    assert np.linalg.norm(a - a[:, J] @ Z) <= 1e-9 * np.linalg.norm(a)
+
+
+def pin_power_improves(O, m=80, n=60, k=6, l=8, reps=40):
+    """On a slowly decaying spectrum the power sketch's rangefinder error
+    ||A - A X^+ X||_F averaged over seeds is below the plain sketch's (the
+    paper's reason for Rand-LUPP-1piter), and both stay above the optimum."""
+    s = inputs.poly_spectrum(min(m, n), 0.5)
+    e_plain = e_pow = 0.0
+    for rep in range(reps):
+        rng = np.random.default_rng([rep, 44])
+        a, om = inputs.small_spectral_case(m, n, k, l, s, 700 + rep)
+        q, _ = np.linalg.qr(O.sketch(a, om).T)
+        e_plain += np.linalg.norm(a - (a @ q) @ q.T)
+        q, _ = np.linalg.qr(O.sketch_power1(a, rng.standard_normal((l, n))).T)
+        e_pow += np.linalg.norm(a - (a @ q) @ q.T)
+    opt = np.sqrt(np.sum(s[l:] ** 2)) * reps
+    a, _ = inputs.small_spectral_case(m, n, k, l, s, 700)
+    opt *= np.linalg.norm(a) / np.sqrt(np.sum(s**2))
+    assert opt <= e_pow < 0.9 * e_plain, (opt, e_pow, e_plain)
+
+
+ALL_PINS += [pin_power_orthonormal, pin_power_diagonal, pin_power_exact_rank, pin_power_improves]

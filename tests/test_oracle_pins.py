@@ -56,6 +56,10 @@ MUTANTS = {
     "FP8 scale one step high": ("    while np.ldexp(mx, e) > E4M3_MAX:\n        e -= 1\n    return e",
                                 "    while np.ldexp(mx, e) > E4M3_MAX:\n        e -= 1\n    return e + 1"),
     "FP8 sketch not unscaled": ("return (Oq @ Aq) * np.ldexp(1.0, -(eo + ea))[None, :]", "return Oq @ Aq"),
+    "power sketch with a second power": ("    Y = A @ _f64(Omega).T\n    return Y.T @ A",
+                                         "    Y = A @ _f64(Omega).T\n    return (Y.T @ A) @ (A.T @ A)"),
+    "power sketch normalised": ("    Y = A @ _f64(Omega).T\n    return Y.T @ A",
+                                "    Y = A @ _f64(Omega).T\n    return Y.T @ A / np.linalg.norm(A)"),
 }
 
 
