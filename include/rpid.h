@@ -44,7 +44,11 @@ typedef enum {
   RPID_FP8_E4M3 = 3  /* OCP FP8 E4M3 (max 448, no infinities) */
 } rpid_dtype;
 
-typedef enum { RPID_RESIDUAL_ID = 0, RPID_RESIDUAL_CUR = 1 } rpid_residual_kind;
+typedef enum {
+  RPID_RESIDUAL_ID = 0,    /* column ID  A ~ A(:, J) Z               */
+  RPID_RESIDUAL_CUR = 1,   /* CUR        A ~ A(:, J) U A(I, :)       */
+  RPID_RESIDUAL_ROW_ID = 2 /* row ID     A ~ Z^T A(I, :), Z is k x m */
+} rpid_residual_kind;
 
 #define RPID_OK 0
 #define RPID_ERR_NONFINITE (-100)   /* NaN/Inf in a matrix handed to pivoting */
@@ -94,14 +98,56 @@ int rpid_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t 
  * Supported (a_t, o_t, x_t): (F64,F64,F64), (F32,F32,F32) and
  * (BF16,BF16,F32).  In the BF16 form Y^T is formed in FP32 and enters the
  * second product as two BF16 terms (about 16 significant bits).
- * 1 <= l <= 512.  Workspace: one transposed copy of A plus the Y^T factors
- * (the context's workspace grows to about m n e_A + 4 l (m + n) bytes).
+ * 1 <= l <= 512.  Workspace: the Y^T factors (about 4 l (m + n) bytes, plus
+ * split-K partials), and a transposed copy of A (m n e_A bytes) except in
+ * the BF16 form when A is 16-byte aligned, lda a multiple of 8, n a multiple
+ * of 64 and m of 8 (then A is read in place).
  * Errors: -position for an invalid argument, RPID_ERR_UNSUPPORTED for other
  * type combinations, RPID_ERR_NOMEM if the workspace cannot grow.
  */
 int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
                        int64_t lda, const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo,
                        void* X, rpid_dtype x_t, int64_t ldx);
+
+/*
+ * Two-sided sketch of the streaming skeleton selection (Alg. 3, step 2): the
+ * row sketch X = Gamma A and the column sketch Y = A Omega^T, the latter
+ * returned transposed as Yt = Y^T = Omega A^T, so that the row-wise pivoting
+ * of Alg. 3, step 4 is rpid_select_columns on Yt (its pivots are rows of A)
+ * and the row ID coefficients are rpid_id_coeffs on Yt.
+ *   A      m x n, lda >= m, type a_t
+ *   Gamma  l x m, ldg >= l, type a_t (independent of Omega)
+ *   Omega  l x n, ldo >= l, type a_t
+ *   X      l x n, ldx >= l, type out_t (output)
+ *   Yt     l x m, ldyt >= l, type out_t (output)
+ * a_t F64 gives out_t F64; F32 and BF16 give out_t F32 (FP32 accumulation).
+ * 1 <= l <= 1024.  BF16 with A 16-byte aligned, lda a multiple of 8, n a
+ * multiple of 64 and m of 8 reads A once: row blocks of at most 64 MiB feed
+ * both products back to back (the second read of a block comes from the
+ * last-level cache); other cases form a transposed copy of A in the
+ * workspace and read A twice.
+ * Errors: -position for an invalid argument (-16: out_t does not match
+ * a_t), RPID_ERR_NOMEM if the workspace cannot grow.
+ */
+int rpid_sketch_two_sided(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                          int64_t lda, const void* Gamma, int64_t ldg, const void* Omega,
+                          int64_t ldo, int64_t l, void* X, int64_t ldx, void* Yt, int64_t ldyt,
+                          rpid_dtype out_t);
+
+/*
+ * Sketch-only CUR core (the cheap form after Alg. 3): U = S^{-1} with
+ * S = A(I, J) the k x k intersection of the skeletons, so that A ~ C U R
+ * without another pass over A (accuracy and stability below those of the
+ * stable core that rpid_cur computes).  S is factored by LU with row
+ * pivoting in FP64.
+ *   A   m x n, lda >= m, type a_t (F64, F32 or BF16)
+ *   J   k column indices, I k row indices (device, int64, 0-based)
+ *   U   k x k FP64 (device, ldu >= k, output)
+ * Returns 0, or t + 1 > 0 if S has an exactly zero pivot at step t (U is
+ * then not written), or -position for an invalid argument.
+ */
+int rpid_cur_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                    int64_t k, const int64_t* J, const int64_t* I, double* U, int64_t ldu);
 
 /*
  * S2, FP8 form -- X = Omega A with A and Omega quantised to OCP E4M3 with
@@ -181,8 +227,12 @@ int rpid_cur(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, 
  * differences (the error measure of the experiments of Sec. 5):
  *   RPID_RESIDUAL_ID : ||A - A(:, J) Z||_F / ||A||_F   (uses J, Z)
  *   RPID_RESIDUAL_CUR: ||A - A(:, J) U A(I, :)||_F / ||A||_F (uses J, I, U)
- * A is m x n of type a_t in {F64, F32, BF16}; Z is k x n FP64 (ldz), U is
- * k x k FP64 (ldu); unused arguments may be NULL.  The products run in FP64
+ *   RPID_RESIDUAL_ROW_ID: ||A - Z^T A(I, :)||_F / ||A||_F (uses I, Z; Z is
+ *     the k x m matrix that rpid_id_coeffs gives for the column sketch Yt of
+ *     rpid_sketch_two_sided, i.e. the row ID A ~ A R^+ R estimated from the
+ *     sketch as Y Y_1^+ after Alg. 3)
+ * A is m x n of type a_t in {F64, F32, BF16}; Z is k x n (k x m for the row
+ * ID) FP64 (ldz), U is k x k FP64 (ldu); unused arguments may be NULL.  The products run in FP64
  * for F64/F32 storage; for BF16 storage on BF16 MFMA with the FP64 factor
  * split into three BF16 terms and FP32 accumulation.  Sums of squares are
  * accumulated in FP64.  *rel_fro (host) receives the ratio; synchronises.

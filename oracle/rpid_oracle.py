@@ -22,7 +22,15 @@ randomized pivoting algorithms for CUR and interpolative decompositions":
                        Remark "Stable CUR", eq. (cur_stable).
 * residuals         -- relative Frobenius errors of the ID A - C Z, the CUR
                        A - C U R, the optimal column ID A - C C^+ A (eq.
-                       def_column_id) and the rangefinder A - A X^+ X (Sec. 2.3).
+                       def_column_id), the row ID A - W R and the rangefinder
+                       A - A X^+ X (Sec. 2.3).
+* sketch_two_sided  -- Alg. 3 (streaming skeleton selection), step 2: the row
+                       sketch X = Gamma A and the column sketch Y = A Omega^T.
+* row_id_coeffs     -- the row ID estimated from the column sketch (after
+                       Alg. 3): A R^+ is replaced by Y Y_1^+ (Y_1 = Y(I_s, :)).
+* cur_sketch_u      -- the CUR core S^{-1}, S = A(I_s, J_s), that needs no
+                       further pass over A (after Alg. 3).
+* decompose_two_sided -- Alg. 3 end to end with the estimates above.
 
 Everything is float64 numpy.  Library primitives used as single steps: matmul,
 QR, triangular/linear solves, SVD (for spectral norms only).
@@ -55,6 +63,11 @@ __all__ = [
     "residuals",
     "rangefinder_error",
     "decompose",
+    "sketch_power1",
+    "sketch_two_sided",
+    "row_id_coeffs",
+    "cur_sketch_u",
+    "decompose_two_sided",
     "NonFiniteInput",
 ]
 
@@ -288,22 +301,24 @@ def rangefinder_error(A, X, k, ord="fro"):
     return float(np.linalg.norm(E, 2) / np.linalg.norm(A, 2))
 
 
-def residuals(A, J, Z=None, I=None, U=None, ord="fro", only=None):
+def residuals(A, J, Z=None, I=None, U=None, ord="fro", only=None, W=None):
     """Relative errors; explicit differences (never an expanded form).
 
     id    ||A - A(:,J) Z|| / ||A||          (Z from the sketch, Sec. 4)
     idopt ||A - C C^+ A|| / ||A||           (eq. def_column_id)
     cur   ||A - C U R|| / ||A||             (eq. def_cur)
     rowopt||A - A R^+ R|| / ||A||           (eq. def_row_id)
-    ``only`` (optional) restricts the work to the listed keys.
+    rowid ||A - W A(I,:)|| / ||A||          (W from the column sketch)
+    ``only`` (optional) restricts the work to the listed keys; J may be None
+    when only row quantities are asked for.
     """
     A = _f64(A)
     nrm = (lambda e: _fro(e)) if ord == "fro" else (lambda e: float(np.linalg.norm(e, 2)))
     na = nrm(A)
-    C = A[:, J]
+    C = A[:, J] if J is not None else None
     want = (lambda key: only is None or key in only)
     out = {}
-    if want("idopt"):
+    if C is not None and want("idopt"):
         qc, _ = np.linalg.qr(C)
         out["idopt"] = nrm(A - qc @ (qc.T @ A)) / na
     if Z is not None and want("id"):
@@ -315,6 +330,8 @@ def residuals(A, J, Z=None, I=None, U=None, ord="fro", only=None):
             out["rowopt"] = nrm(A - (A @ qr_) @ qr_.T) / na
         if U is not None and want("cur"):
             out["cur"] = nrm(A - (C @ _f64(U)) @ R) / na
+        if W is not None and want("rowid"):
+            out["rowid"] = nrm(A - _f64(W) @ R) / na
     return out
 
 
@@ -352,4 +369,59 @@ def decompose(A, Omega, k, gaps=False, want_cur=True):
             out["gap_I"] = row["gap"]
         if row["status"] == 0:
             out["U"] = cur_u(A, J, row["J"])
+    return out
+
+
+# --------------------------------------------------------------------------
+# Alg. 3: streaming (two-sided, single-pass) skeleton selection, and the
+# estimates of the ID and CUR that avoid a further pass over A
+# --------------------------------------------------------------------------
+def sketch_two_sided(A, Gamma, Omega):
+    """Alg. 3, step 2 with independent embeddings Gamma (l x m) and Omega
+    (l x n): X = Gamma A (l x n) and Y = A Omega^T (m x l)."""
+    A = _f64(A)
+    return _f64(Gamma) @ A, A @ _f64(Omega).T
+
+
+def row_id_coeffs(Y, I, k=None):
+    """W (m x k) with A ~ W A(I, :), estimated from the column sketch: A R^+
+    is replaced by Y Y_1^+ with Y_1 = Y(I, :).  With k < l the first k
+    columns are used, Y_k = Y(:, 0:k) and W = Y_k Y_k(I, :)^{-1} (the row
+    analogue of Z in Sec. 4); W(I, :) = I exactly."""
+    Y = _f64(Y)
+    I = np.asarray(I, dtype=np.int64)
+    if k is None:
+        k = I.shape[0]
+    I = I[:k]
+    Yk = Y[:, :k]
+    # W Y_1 = Y_k  <=>  Y_1^T W^T = Y_k^T
+    W = np.linalg.solve(Yk[I, :].T, Yk.T).T
+    W[I, :] = np.eye(k)
+    return W
+
+
+def cur_sketch_u(A, J, I):
+    """U = S^{-1} with S = A(I, J), the core of the CUR C S^{-1} R."""
+    A = _f64(A)
+    S = A[np.ix_(np.asarray(I, dtype=np.int64), np.asarray(J, dtype=np.int64))]
+    return np.linalg.solve(S, np.eye(S.shape[0]))
+
+
+def decompose_two_sided(A, Gamma, Omega, k, gaps=False):
+    """Alg. 3: both sketches, column LUPP on X -> J, row LUPP on Y -> I; then
+    Z from X (Sec. 4), W from Y, the cheap core S^{-1} and the stable core
+    C^+ A R^+ for comparison."""
+    A = _f64(A)
+    X, Y = sketch_two_sided(A, Gamma, Omega)
+    col = lupp_colwise(X, k, gaps=gaps)
+    row = lupp_rowwise(Y, k, gaps=gaps)
+    out = dict(X=X, Y=Y, J=col["J"], I=row["J"], status_J=col["status"], status_I=row["status"])
+    if gaps:
+        out["gap_J"], out["gap_I"] = col["gap"], row["gap"]
+    if col["status"] != 0 or row["status"] != 0:
+        return out
+    out["Z"] = id_coeffs(X, col["J"], k)
+    out["W"] = row_id_coeffs(Y, row["J"], k)
+    out["U_sketch"] = cur_sketch_u(A, col["J"], row["J"])
+    out["U"] = cur_u(A, col["J"], row["J"])
     return out

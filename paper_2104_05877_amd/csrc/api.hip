@@ -301,9 +301,14 @@ static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, i
     Qp = Z;
     ldq = ldz;
   } else {
-    // P = C U, Q = R = A(I, :)
-    RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, Q, m));  // C into Q scratch
-    RPID_CHECK(dgemm(ctx, false, false, m, k, k, 1.0, Q, m, U, ldu, 0.0, P, m, o_tmp));
+    if (which == RPID_RESIDUAL_CUR) {
+      // P = C U, Q = R = A(I, :)
+      RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, Q, m));  // C into Q scratch
+      RPID_CHECK(dgemm(ctx, false, false, m, k, k, 1.0, Q, m, U, ldu, 0.0, P, m, o_tmp));
+    } else {
+      // row ID: P = Z^T (Z is k x m), Q = R = A(I, :)
+      RPID_CHECK(transpose_copy<double>(ctx, k, m, Z, ldz, P, m));
+    }
     RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, Q, k));
     Qp = Q;
     ldq = k;
@@ -513,7 +518,37 @@ __global__ void add_halves_f32_kernel(int64_t l, int64_t n, const float* X2, int
   }
 }
 
+// X(r, j) = sum_b parts[b](r, j) in block order (parts: nb x l x n, FP32)
+__global__ void sum_blocks_f32_kernel(int nb, int64_t l, int64_t n, const float* parts, float* X,
+                                      int64_t ldx) {
+  const int64_t total = l * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    float s = parts[e];
+    for (int b = 1; b < nb; ++b) s += parts[(int64_t)b * total + e];
+    X[e % l + (e / l) * ldx] = s;
+  }
+}
+
+// U(:, J[t]) = P(:, t), k x k
+__global__ void scatter_cols_f64_kernel(int64_t k, const double* P, const int64_t* J, double* U,
+                                        int64_t ldu) {
+  const int64_t total = k * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % k, t = e / k;
+    U[r + J[t] * ldu] = P[e];
+  }
+}
+
 }  // namespace
+
+// Shapes and alignments for which the BF16 transposed-A sketch runs (the
+// kernel checks them again and reports RPID_ERR_UNSUPPORTED otherwise).
+static bool at_bf16_fits(const void* A, int64_t m, int64_t n, int64_t lda, int64_t l) {
+  return ((uintptr_t)A % 16 == 0) && (lda * 2) % 16 == 0 && n % 64 == 0 && m % 8 == 0 &&
+         64 * lda * 2 + m * 2 < ((int64_t)1 << 31) && l * n * 2 < ((int64_t)1 << 31) && l <= 1024;
+}
 
 int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
                        int64_t lda, const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo,
@@ -537,7 +572,8 @@ int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, i
   const size_t acc = f64 ? 8 : 4;
   const int64_t l2 = bf ? 2 * l : l;  // rows of the second product's left factor
   Carve cv;
-  const size_t o_at = cv.take<char>((size_t)m * n * es);
+  const bool in_place = bf && at_bf16_fits(A, m, n, lda, l);
+  const size_t o_at = in_place ? 0 : cv.take<char>((size_t)m * n * es);
   const size_t o_p1 = cv.take<char>((size_t)n * l * es);
   const size_t o_yt = cv.take<char>((size_t)l * m * acc);
   const size_t o_p2 = cv.take<char>((size_t)m * l2 * es);
@@ -563,9 +599,15 @@ int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, i
     RPID_CHECK(transpose_copy<float>(ctx, l, m, (const float*)yt, l, (float*)p2, m));
     return sketch_f32(ctx, (const float*)p2, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
   }
-  RPID_CHECK(transpose_copy<uint16_t>(ctx, m, n, (const uint16_t*)A, lda, (uint16_t*)at, n));
   RPID_CHECK(transpose_copy<uint16_t>(ctx, l, n, (const uint16_t*)Omega, ldo, (uint16_t*)p1, n));
-  RPID_CHECK(sketch_bf16(ctx, (const uint16_t*)p1, n, (const uint16_t*)at, n, n, m, l, (float*)yt, l, ws_sk));
+  if (at_bf16_fits(A, m, n, lda, l)) {
+    // Y^T = Omega A^T straight from A
+    RPID_CHECK(sketch_at_bf16(ctx, (const uint16_t*)p1, n, (const uint16_t*)A, lda, m, n, l, (float*)yt, l,
+                              ws_sk));
+  } else {
+    RPID_CHECK(transpose_copy<uint16_t>(ctx, m, n, (const uint16_t*)A, lda, (uint16_t*)at, n));
+    RPID_CHECK(sketch_bf16(ctx, (const uint16_t*)p1, n, (const uint16_t*)at, n, n, m, l, (float*)yt, l, ws_sk));
+  }
   dim3 grid((unsigned)((m + 31) / 32), (unsigned)((l + 31) / 32));
   hipLaunchKernelGGL(split_t_bf16_kernel, grid, dim3(256), 0, ctx->stream, l, m, (const float*)yt, l,
                      (uint16_t*)p2, m);
@@ -576,6 +618,155 @@ int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, i
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(add_halves_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, l, n, x2,
                      l2, (float*)X, ldx);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+
+// ---------------------------------------------------------------------------
+int rpid_sketch_two_sided(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                          int64_t lda, const void* Gamma, int64_t ldg, const void* Omega,
+                          int64_t ldo, int64_t l, void* X, int64_t ldx, void* Yt, int64_t ldyt,
+                          rpid_dtype out_t) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (!(a_t == RPID_F64 || a_t == RPID_F32 || a_t == RPID_BF16)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (!Gamma) return -7;
+  if (ldg < l) return -8;
+  if (!Omega) return -9;
+  if (ldo < l) return -10;
+  if (l < 1 || l > 1024) return -11;
+  if (!X) return -12;
+  if (ldx < l) return -13;
+  if (!Yt) return -14;
+  if (ldyt < l) return -15;
+  if (out_t != (a_t == RPID_F64 ? RPID_F64 : RPID_F32)) return -16;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  const size_t es = esize(a_t);
+  const int acc = a_t == RPID_F64 ? 8 : 4;
+  const bool in_place = a_t == RPID_BF16 && at_bf16_fits(A, m, n, lda, l);
+  // Row blocks of A small enough to stay in the last-level cache between the
+  // two products of a block (64 MiB, a multiple of 64 rows).
+  int64_t mb = m;
+  if (in_place) {
+    mb = ((int64_t)64 << 20) / (n * 2);
+    mb = std::max<int64_t>(64, mb / 64 * 64);
+    if (mb >= m) mb = m;
+  }
+  const int64_t nb = (m + mb - 1) / mb;
+  Carve cv;
+  const size_t o_gt = cv.take<char>((size_t)m * l * es);
+  const size_t o_ot = cv.take<char>((size_t)n * l * es);
+  const size_t o_at = in_place ? 0 : cv.take<char>((size_t)m * n * es);
+  const size_t o_parts = nb > 1 ? cv.take<float>((size_t)nb * l * n) : 0;
+  const size_t ws_sk = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, ws_sk + std::max(sketch_workspace_bytes(ctx, m, n, l, acc),
+                                                    sketch_workspace_bytes(ctx, n, m, l, acc))));
+  char* gt = ws_ptr<char>(ctx, o_gt);
+  char* ot = ws_ptr<char>(ctx, o_ot);
+  char* at = ws_ptr<char>(ctx, o_at);
+  if (a_t == RPID_F64) {
+    RPID_CHECK(transpose_copy<double>(ctx, l, m, (const double*)Gamma, ldg, (double*)gt, m));
+    RPID_CHECK(transpose_copy<double>(ctx, l, n, (const double*)Omega, ldo, (double*)ot, n));
+    RPID_CHECK(sketch_f64(ctx, (const double*)gt, m, (const double*)A, lda, m, n, l, (double*)X, ldx, ws_sk));
+    RPID_CHECK(transpose_copy<double>(ctx, m, n, (const double*)A, lda, (double*)at, n));
+    return sketch_f64(ctx, (const double*)ot, n, (const double*)at, n, n, m, l, (double*)Yt, ldyt, ws_sk);
+  }
+  if (a_t == RPID_F32) {
+    RPID_CHECK(transpose_copy<float>(ctx, l, m, (const float*)Gamma, ldg, (float*)gt, m));
+    RPID_CHECK(transpose_copy<float>(ctx, l, n, (const float*)Omega, ldo, (float*)ot, n));
+    RPID_CHECK(sketch_f32(ctx, (const float*)gt, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk));
+    RPID_CHECK(transpose_copy<float>(ctx, m, n, (const float*)A, lda, (float*)at, n));
+    return sketch_f32(ctx, (const float*)ot, n, (const float*)at, n, n, m, l, (float*)Yt, ldyt, ws_sk);
+  }
+  const uint16_t* Ab = (const uint16_t*)A;
+  RPID_CHECK(transpose_copy<uint16_t>(ctx, l, m, (const uint16_t*)Gamma, ldg, (uint16_t*)gt, m));
+  RPID_CHECK(transpose_copy<uint16_t>(ctx, l, n, (const uint16_t*)Omega, ldo, (uint16_t*)ot, n));
+  if (!in_place) {
+    RPID_CHECK(sketch_bf16(ctx, (const uint16_t*)gt, m, Ab, lda, m, n, l, (float*)X, ldx, ws_sk));
+    RPID_CHECK(transpose_copy<uint16_t>(ctx, m, n, Ab, lda, (uint16_t*)at, n));
+    return sketch_bf16(ctx, (const uint16_t*)ot, n, (const uint16_t*)at, n, n, m, l, (float*)Yt, ldyt, ws_sk);
+  }
+  // one pass over A: each row block feeds both products back to back
+  float* parts = nb > 1 ? ws_ptr<float>(ctx, o_parts) : nullptr;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t i0 = b * mb, mi = std::min(mb, m - i0);
+    float* xo = nb > 1 ? parts + b * l * n : (float*)X;
+    const int64_t ldxo = nb > 1 ? l : ldx;
+    RPID_CHECK(sketch_bf16(ctx, (const uint16_t*)gt + i0, m, Ab + i0, lda, mi, n, l, xo, ldxo, ws_sk));
+    RPID_CHECK(sketch_at_bf16(ctx, (const uint16_t*)ot, n, Ab + i0, lda, mi, n, l, (float*)Yt + i0 * ldyt,
+                              ldyt, ws_sk));
+  }
+  if (nb > 1) {
+    int64_t blocks = std::min<int64_t>((l * n + 255) / 256, 8192);
+    hipLaunchKernelGGL(sum_blocks_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, (int)nb, l,
+                       n, parts, (float*)X, ldx);
+    RPID_HIP_CHECK(hipGetLastError());
+  }
+  return RPID_OK;
+}
+
+int rpid_cur_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                    int64_t k, const int64_t* J, const int64_t* I, double* U, int64_t ldu) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (!(a_t == RPID_F64 || a_t == RPID_F32 || a_t == RPID_BF16)) return -3;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (k < 1 || k > m || k > n || k > 1024) return -7;
+  if (!J) return -8;
+  if (!I) return -9;
+  if (!U) return -10;
+  if (ldu < k) return -11;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_status = cv.take<int64_t>(8);
+  const size_t o_C = cv.take<double>((size_t)m * k);
+  const size_t o_S = cv.take<double>((size_t)k * k);
+  const size_t o_Jp = cv.take<int64_t>((size_t)k);
+  const size_t o_L = cv.take<double>((size_t)k * k);
+  const size_t o_Uf = cv.take<double>((size_t)k * k);
+  const size_t o_dg = cv.take<double>((size_t)k);
+  const size_t o_LJ = cv.take<double>((size_t)k * k);
+  const size_t o_W = cv.take<double>((size_t)k * k);
+  const size_t o_WU = cv.take<double>((size_t)k * k);
+  const size_t o_P = cv.take<double>((size_t)k * k);
+  const size_t o_lupp = cv.off;
+  const size_t o_tmp = o_lupp + lupp_workspace_bytes(ctx, k, k, 8);
+  RPID_CHECK(ensure_workspace(ctx, o_tmp + (size_t)64 * k * k * sizeof(double) + 4096));
+  int64_t* status_dev = ws_ptr<int64_t>(ctx, o_status);
+  double* C = ws_ptr<double>(ctx, o_C);
+  double* S = ws_ptr<double>(ctx, o_S);
+  int64_t* Jp = ws_ptr<int64_t>(ctx, o_Jp);
+  double* L = ws_ptr<double>(ctx, o_L);
+  double* Uf = ws_ptr<double>(ctx, o_Uf);
+  double* LJ = ws_ptr<double>(ctx, o_LJ);
+  double* W = ws_ptr<double>(ctx, o_W);
+  double* WU = ws_ptr<double>(ctx, o_WU);
+  double* P = ws_ptr<double>(ctx, o_P);
+  // S = A(I, J) in FP64
+  switch (a_t) {
+    case RPID_F64: RPID_CHECK(gather_columns<double, double>(ctx, m, k, (const double*)A, lda, n, J, C, m)); break;
+    case RPID_F32: RPID_CHECK(gather_columns<float, double>(ctx, m, k, (const float*)A, lda, n, J, C, m)); break;
+    default: RPID_CHECK(gather_columns<uint16_t, double>(ctx, m, k, (const uint16_t*)A, lda, n, J, C, m)); break;
+  }
+  RPID_CHECK(gather_rows<double, double>(ctx, k, k, C, m, m, I, S, k));
+  // row LUPP of S: S(Jp, :) = L(Jp, :) U', so S^{-1}(:, Jp[t]) = (U'^{-1} L(Jp, :)^{-1})(:, t)
+  RPID_CHECK(lupp_panel<double>(ctx, S, 1, k, k, k, Jp, L, k, Uf, k, ws_ptr<double>(ctx, o_dg), o_lupp,
+                                status_dev));
+  int64_t st = 0;
+  RPID_CHECK(read_status(ctx, status_dev, &st));
+  if (st != 0) return (int)st;
+  RPID_CHECK(gather_rows<double, double>(ctx, k, k, L, k, k, Jp, LJ, k));
+  RPID_CHECK(tri_inverse(ctx, k, LJ, k, true, true, W, k, o_tmp));
+  RPID_CHECK(tri_inverse(ctx, k, Uf, k, false, false, WU, k, o_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, WU, k, W, k, 0.0, P, k, o_tmp));
+  const int64_t blocks = std::min<int64_t>((k * k + 255) / 256, 1024);
+  hipLaunchKernelGGL(scatter_cols_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, k, P, Jp, U,
+                     ldu);
   RPID_HIP_CHECK(hipGetLastError());
   return RPID_OK;
 }
@@ -740,17 +931,17 @@ int rpid_residual(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_
                   int64_t lda, int64_t k, const int64_t* J, const double* Z, int64_t ldz,
                   const int64_t* I, const double* U, int64_t ldu, double* rel_fro) {
   if (!ctx) return -1;
-  if (which != RPID_RESIDUAL_ID && which != RPID_RESIDUAL_CUR) return -2;
+  if (which != RPID_RESIDUAL_ID && which != RPID_RESIDUAL_CUR && which != RPID_RESIDUAL_ROW_ID) return -2;
   if (!A) return -3;
   if (!(a_t == RPID_F64 || a_t == RPID_F32 || a_t == RPID_BF16)) return -4;
   if (m < 1) return -5;
   if (n < 1) return -6;
   if (lda < m) return -7;
   if (k < 1 || k > m || k > n || k > 1024) return -8;
-  if (!J) return -9;
-  if (which == RPID_RESIDUAL_ID && !Z) return -10;
-  if (which == RPID_RESIDUAL_ID && ldz < k) return -11;
-  if (which == RPID_RESIDUAL_CUR && !I) return -12;
+  if (!J && which != RPID_RESIDUAL_ROW_ID) return -9;
+  if (which != RPID_RESIDUAL_CUR && !Z) return -10;
+  if (which != RPID_RESIDUAL_CUR && ldz < k) return -11;
+  if (which != RPID_RESIDUAL_ID && !I) return -12;
   if (which == RPID_RESIDUAL_CUR && !U) return -13;
   if (which == RPID_RESIDUAL_CUR && ldu < k) return -14;
   if (!rel_fro) return -15;

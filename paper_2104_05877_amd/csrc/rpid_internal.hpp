@@ -117,6 +117,11 @@ int sketch_e4m3(rpid_ctx ctx, const uint8_t* Pt, int64_t ldp, const uint8_t* A, 
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
 int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
+// Y^T = Omega A^T (l x m) for a column-major m x n BF16 A read in place;
+// Ot = Omega^T is n x l (ldot).  RPID_ERR_UNSUPPORTED when the shape or the
+// alignment does not suit the kernel (n % 64, m % 8, 16-byte alignment).
+int sketch_at_bf16(rpid_ctx ctx, const uint16_t* Ot, int64_t ldot, const uint16_t* A, int64_t lda,
+                   int64_t m, int64_t n, int64_t l, float* Yt, int64_t ldyt, size_t ws_off);
 size_t sketch_workspace_bytes(rpid_ctx ctx, int64_t m, int64_t n, int64_t l, int elem_acc);
 bool residual_stream_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* R,
                           int64_t ldr, const uint16_t* Pt, int64_t ldpt, const uint16_t* Q,

@@ -419,12 +419,32 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(SketchArgs<TE> a) {
 //    stage s done, those of s+1 still in flight) hands the stage over.
 //  * Stages past the K-range (at most two, to fill the last rotation) use
 //    empty descriptors: they load zeros, touch no memory and add nothing.
+//  * AT (BF16 only): the contraction runs along the columns of A instead of
+//    its rows, i.e. the output is Omega A^T (l x m) for a column-major m x n
+//    A, with Pt = Omega^T (n x l).  A stage of A is then 64 columns x 128
+//    rows, copied as it lies in memory (256-byte LDS rows, one per column,
+//    32-byte chunks XOR-swizzled by the column), and the B operand (8
+//    consecutive columns of one row per lane) is read with the LDS transpose
+//    read: within each 16-lane group, lane s reads 4 consecutive rows of one
+//    column (column s / 4, rows 4 (s % 4) ..), and lane t receives element
+//    t % 4 of lanes t / 4 + 4 e, e = 0..3 -- row t of the tile at 4
+//    consecutive columns.  Rows of A past m read whatever lies there (only
+//    their own, dropped, outputs see it) or zeros past the matrix's last
+//    element (the descriptor's range ends there).
 typedef __attribute__((address_space(3))) void lds_void_t;
+typedef short v4s16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4s16 lds_v4s16_t;
+
+// 32-byte chunk swizzle of the transposed A stage: column kr of the stage
+// stores logical chunk c at chunk c ^ at_swz(kr).  The 16 columns that one
+// transpose read touches (kr = 8 g + 4 h + 0..3, g = 0..3) map to 8 distinct
+// chunks.
+__device__ __forceinline__ int at_swz(int kr) { return (kr & 7) ^ (((kr >> 3) & 1) << 2); }
 
 // raw buffer descriptor word 3 for gfx9-family loads (32-bit data format)
 constexpr int BUF_WORD3 = 0x00020000;
 
-template <typename TE, int RTW, int CTW, bool RESID>
+template <typename TE, int RTW, int CTW, bool RESID, bool AT = false>
 __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a) {
   using M = MT<TE>;
   using AccV = typename M::AccV;
@@ -445,6 +465,7 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
   constexpr int IPS = (NI + SUB - 1) / SUB;   // direct loads slotted into each k-step
   static_assert(SUB >= 1 && 4 * VB * SUB == SB, "stage must hold whole operand k-steps");
   static_assert(NI <= 63, "vmcnt immediate of the hand-over");
+  static_assert(!AT || (sizeof(TE) == 2 && !RESID && ACOLS == 128), "transposed A: BF16, 128 rows");
 
   __shared__ __attribute__((aligned(1024))) char o0[OBYTES];
   __shared__ __attribute__((aligned(1024))) char o1[OBYTES];
@@ -480,15 +501,28 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
   const uint32_t orange = (uint32_t)((int64_t)a.l * a.ldp * (int64_t)sizeof(TE));
   const uint32_t orow = (uint32_t)(a.ldp * (int64_t)sizeof(TE));
   const uint32_t ooff0 = (uint32_t)(row_base + 8 * wid + (lane >> 3)) * orow + (uint32_t)(swz_st * 16);
-  const char* abase = reinterpret_cast<const char*>(a.A + kbeg);
+  const char* abase = reinterpret_cast<const char*>(AT ? a.A + kbeg * a.lda : a.A + kbeg);
   const uint32_t arange = (uint32_t)(a.n * a.lda * (int64_t)sizeof(TE));
   const uint32_t acol = (uint32_t)(a.lda * (int64_t)sizeof(TE));
+  // AT: bytes from the start of a stage to the end of A's last element,
+  // minus those of the stages before it (clamped to the 32-bit range)
+  const int64_t at_end = ((a.m - kbeg - 1) * a.lda + a.n) * (int64_t)sizeof(TE);
+  const int64_t at_step = (int64_t)BKS * a.lda * (int64_t)sizeof(TE);
   uint32_t aoffs[NIA];
 #pragma unroll
   for (int i = 0; i < NIA; ++i) {
-    int64_t col = col0 + 8 * (wid + 4 * i) + (lane >> 3);
-    if (col >= a.n) col = 0;
-    aoffs[i] = (uint32_t)col * acol + (uint32_t)(swz_st * 16);
+    if constexpr (AT) {
+      // load i of this wave fills stage columns kr = 4 (w + 4 i) .. +4; lane
+      // -> (column kr + lane / 16, 16-byte slot lane % 16)
+      const int kr = 4 * (wid + 4 * i) + (lane >> 4);
+      const int slot = lane & 15;
+      const int chunk = (slot >> 1) ^ at_swz(kr);
+      aoffs[i] = (uint32_t)kr * acol + (uint32_t)((col0 + chunk * 16 + (slot & 1) * 8) * (int64_t)sizeof(TE));
+    } else {
+      int64_t col = col0 + 8 * (wid + 4 * i) + (lane >> 3);
+      if (col >= a.n) col = 0;
+      aoffs[i] = (uint32_t)col * acol + (uint32_t)(swz_st * 16);
+    }
   }
 
   AccV acc[RTW][CTW];
@@ -519,8 +553,15 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
                                              st < nst ? (int)orange : 0, BUF_WORD3);
   };
   auto arsrc = [&](int st) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(abase + (int64_t)st * SB), (short)0,
-                                             st < nst ? (int)arange : 0, BUF_WORD3);
+    if constexpr (AT) {
+      int64_t rg = at_end - (int64_t)st * at_step;
+      if (rg > 0x7fffffff) rg = 0x7fffffff;
+      return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(abase + (int64_t)st * at_step), (short)0,
+                                               st < nst ? (int)rg : 0, BUF_WORD3);
+    } else {
+      return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(abase + (int64_t)st * SB), (short)0,
+                                               st < nst ? (int)arange : 0, BUF_WORD3);
+    }
   };
   // direct load j (0 .. NI-1) of a stage: Omega loads first, then A
   auto dma = [&](__amdgpu_buffer_rsrc_t ors, __amdgpu_buffer_rsrc_t ars, char* ob, char* ab, int j) {
@@ -530,6 +571,8 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
     else
       __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, (lds_void_t*)(ab + 8 * (wid + 4 * (j - NIO)) * SB),
                                                16, (int)aoffs[j - NIO], 0, 0, 0);
+    // (AT: load j - NIO fills 1 KB = stage columns 4 (w + 4 i) .. +4, the
+    // same LDS bytes as 8 rows of 128 bytes)
   };
   auto load_stage = [&](int st, char* ob, char* ab) {
     const auto ors = orsrc(st);
@@ -551,13 +594,30 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
 #pragma unroll
     for (int sub = 0; sub < SUB; ++sub) {
       Frag<TE> af[RTW], bf[CTW];
+      if constexpr (AT) {
+        // columns sub*32 + 8 q + 4 h + (c16 / 4) of the stage, rows
+        // 4 (c16 % 4) .. +4 of tile c
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kr = sub * 32 + 8 * q + 4 * h + (c16 >> 2);
+          const int sw = at_swz(kr);
+#pragma unroll
+          for (int c = 0; c < CTW; ++c) {
+            const int chunk = (wc * CTW + c) ^ sw;
+            const v4s16 t = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                (lds_v4s16_t*)(ab + kr * 256 + chunk * 32 + 8 * (c16 & 3)));
+            __builtin_memcpy(reinterpret_cast<char*>(bf[c].v) + 8 * h, &t, 8);
+          }
+        }
+      }
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         const int slot = (sub * 4 * NP + q * NP + p) ^ swz;
 #pragma unroll
         for (int c = 0; c < CTW; ++c)
-          reinterpret_cast<uint4*>(bf[c].v)[p] =
-              *reinterpret_cast<const uint4*>(ab + a_rd + c * 16 * SB + slot * 16);
+          if constexpr (!AT)
+            reinterpret_cast<uint4*>(bf[c].v)[p] =
+                *reinterpret_cast<const uint4*>(ab + a_rd + c * 16 * SB + slot * 16);
 #pragma unroll
         for (int r = 0; r < RTW; ++r)
           reinterpret_cast<uint4*>(af[r].v)[p] =
@@ -576,7 +636,7 @@ __global__ __launch_bounds__(256, 1) void sketch_stream_kernel(SketchArgs<TE> a)
       // of stage st + 2 slotted in between
       constexpr int NM = RTW * CTW * KMF;
       constexpr int GAP = NM / (IPS + 1) > 0 ? NM / (IPS + 1) : 1;
-      __builtin_amdgcn_sched_group_barrier(0x100, (RTW + CTW) * NP, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, RTW * NP + (AT ? 2 * CTW : CTW * NP), 0);
 #pragma unroll
       for (int v = 0; v < IPS; ++v) {
         __builtin_amdgcn_sched_group_barrier(0x008, GAP, 0);
@@ -732,12 +792,12 @@ static void launch_sketch(rpid_ctx ctx, const SketchArgs<TE>& a, int64_t grid, b
   }
 }
 
-template <typename TE, int CTW>
+template <typename TE, int CTW, bool AT = false>
 static void launch_stream(rpid_ctx ctx, const SketchArgs<TE>& a, int64_t grid, int rtw) {
   switch (rtw) {
 #define RPID_STREAM_RTW(R)                                                                  \
   case R:                                                                                  \
-    hipLaunchKernelGGL((sketch_stream_kernel<TE, R, CTW, false>), dim3((unsigned)grid), dim3(256), 0, \
+    hipLaunchKernelGGL((sketch_stream_kernel<TE, R, CTW, false, AT>), dim3((unsigned)grid), dim3(256), 0, \
                        ctx->stream, a);                                                    \
     break;
     RPID_STREAM_RTW(1)
@@ -762,11 +822,13 @@ struct StreamCTW {
 
 // The streaming kernel (BF16, FP8, FP32 operands): aligned operands, K a
 // whole number of 128-byte stages, 32-bit operand offsets.  Returns false if
-// it does not apply.
-template <typename TE>
+// it does not apply.  AT (BF16): the product is Pt^T A^T for a column-major
+// A of `n` rows and `m` columns (K = m runs along its columns); the output
+// is l x n as always.  `max_split` caps the split-K count.
+template <typename TE, bool AT = false>
 static bool sketch_stream(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int64_t lda,
                           int64_t m, int64_t n, int64_t l, typename MT<TE>::Acc* X, int64_t ldx,
-                          size_t ws_off, int* err) {
+                          size_t ws_off, int* err, int64_t max_split = 16) {
   using Acc = typename MT<TE>::Acc;
   constexpr int CTW = StreamCTW<TE>::value;
   constexpr int BKS = 128 / (int)sizeof(TE);
@@ -775,7 +837,13 @@ static bool sketch_stream(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, 
   const bool aligned = ((uintptr_t)A % 16 == 0) && ((uintptr_t)Pt % 16 == 0) && (lda * sz) % 16 == 0 &&
                        (ldp * sz) % 16 == 0;
   if (!aligned || m % BKS != 0) return false;
-  if (n * lda * sz >= ((int64_t)1 << 31) || l * ldp * sz >= ((int64_t)1 << 31)) return false;
+  if (AT) {
+    // 16-byte pieces never straddle the last row; in-stage offsets fit 32 bits
+    if (n % 8 != 0 || lda < n || (int64_t)BKS * lda * sz + n * sz >= ((int64_t)1 << 31)) return false;
+  } else if (n * lda * sz >= ((int64_t)1 << 31)) {
+    return false;
+  }
+  if (l * ldp * sz >= ((int64_t)1 << 31)) return false;
   // l-chunks of at most 2 RTWMAX row tiles, as even as the tile count allows
   const int ltiles = (int)((l + 15) / 16);
   const int lchunks = (ltiles + 2 * RTWMAX - 1) / (2 * RTWMAX);
@@ -784,7 +852,7 @@ static bool sketch_stream(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, 
   const int64_t kst = m / BKS;  // stages
   int64_t split = (int64_t)ctx->num_cu / (strips * lchunks);
   if (split > kst) split = kst;
-  if (split > 16) split = 16;
+  if (split > max_split) split = max_split;
   if (split < 1) split = 1;
   SketchArgs<TE> a{};
   a.Pt = Pt;
@@ -814,7 +882,7 @@ static bool sketch_stream(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, 
     a.out_split_stride = l * n;
     a.vec_out = (l % 4 == 0);
   }
-  launch_stream<TE, CTW>(ctx, a, split * strips * lchunks, rtw);
+  launch_stream<TE, CTW, AT>(ctx, a, split * strips * lchunks, rtw);
   *err = hipGetLastError() == hipSuccess ? RPID_OK : RPID_ERR_HIP;
   if (*err == RPID_OK && split > 1) {
     int64_t blocks = (l * n + 255) / 256;
@@ -961,6 +1029,20 @@ int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A
       sketch_stream<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err))
     return err;
   return sketch_impl<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+}
+
+// Y^T = Omega A^T (l x m) for a column-major m x n BF16 A, with Ot = Omega^T
+// (n x l, BF16): the streaming kernel with K along the columns of A, so A is
+// read in place.  RPID_ERR_UNSUPPORTED (nothing launched) when the shapes or
+// alignments do not suit it (n a multiple of 64, m of 8, 16-byte aligned
+// operands and leading dimensions).
+int sketch_at_bf16(rpid_ctx ctx, const uint16_t* Ot, int64_t ldot, const uint16_t* A, int64_t lda,
+                   int64_t m, int64_t n, int64_t l, float* Yt, int64_t ldyt, size_t ws_off) {
+  int err = RPID_OK;
+  if (l < 1 || l > 1024 || m < 1 || n < 1) return RPID_ERR_UNSUPPORTED;
+  if (!sketch_stream<uint16_t, true>(ctx, Ot, ldot, A, lda, n, m, l, Yt, ldyt, ws_off, &err))
+    return RPID_ERR_UNSUPPORTED;
+  return err;
 }
 
 }  // namespace rpid

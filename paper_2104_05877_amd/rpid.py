@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librpid.so")
 
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
-RESIDUAL_ID, RESIDUAL_CUR = 0, 1
+RESIDUAL_ID, RESIDUAL_CUR, RESIDUAL_ROW_ID = 0, 1, 2
 MLP_IN, MLP_H = 512, 128
 MLP_NPARAM = 128 * 512 + 128 + 128 * 128 + 128 + 128 + 1
 
@@ -46,6 +46,8 @@ _SIGS = {
     "rpid_version": (_i, []),
     "rpid_sketch": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
     "rpid_sketch_power1": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
+    "rpid_sketch_two_sided": (_i, [_P, _P, _i, _I, _I, _I, _P, _I, _P, _I, _I, _P, _I, _P, _I, _i]),
+    "rpid_cur_sketch": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _P, _I]),
     "rpid_sketch_fp8": (_i, [_P, _P, _I, _I, _I, _P, _I, _I, _P, _I]),
     "rpid_select_columns": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, ctypes.POINTER(_I)]),
     "rpid_id_coeffs": (
@@ -188,6 +190,39 @@ def rpid_sketch_power1(ctx: Context, A: torch.Tensor, Omega: torch.Tensor) -> to
     return X
 
 
+def rpid_sketch_two_sided(ctx: Context, A: torch.Tensor, Gamma: torch.Tensor, Omega: torch.Tensor):
+    """Alg. 3, step 2: X = Gamma A (l x n) and Yt = Omega A^T (l x m, the
+    column sketch Y = A Omega^T transposed).  Gamma is l x m, Omega l x n.
+    BF16 inputs give FP32 sketches."""
+    pa, m, n, lda = colmajor(A)
+    pg, l, m2, ldg = colmajor(Gamma)
+    po, l2, n2, ldo = colmajor(Omega)
+    if m2 != m or n2 != n or l2 != l:
+        raise ValueError("Gamma must be l x m and Omega l x n")
+    if Gamma.dtype != A.dtype or Omega.dtype != A.dtype:
+        raise ValueError("Gamma and Omega must have A's dtype")
+    out_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
+    X = empty_colmajor(l, n, out_dtype, A.device)
+    Yt = empty_colmajor(l, m, out_dtype, A.device)
+    px, _, _, ldx = colmajor(X)
+    py, _, _, ldy = colmajor(Yt)
+    s = lib().rpid_sketch_two_sided(ctx.handle, pa, dtype_code(A), m, n, lda, pg, ldg, po, ldo, l, px, ldx,
+                                    py, ldy, dtype_code(X))
+    _check("rpid_sketch_two_sided", s)
+    return X, Yt
+
+
+def rpid_cur_sketch(ctx: Context, A: torch.Tensor, k: int, J: torch.Tensor, I: torch.Tensor):
+    """U = A(I, J)^{-1} (k x k FP64), the sketch-only CUR core.  Returns
+    (U, status); status > 0 reports an exactly zero pivot of A(I, J)."""
+    pa, m, n, lda = colmajor(A)
+    U = empty_colmajor(k, k, torch.float64, A.device)
+    s = lib().rpid_cur_sketch(ctx.handle, pa, dtype_code(A), m, n, lda, k, J.data_ptr(), I.data_ptr(),
+                              U.data_ptr(), U.stride(1))
+    _check("rpid_cur_sketch", s, allow_positive=True)
+    return U, s
+
+
 def rpid_sketch_fp8(ctx: Context, A: torch.Tensor, Omega: torch.Tensor) -> torch.Tensor:
     """FP8 (E4M3, power-of-two scaled) sketch of FP32 A; FP32 X."""
     pa, m, n, lda = colmajor(A)
@@ -244,11 +279,12 @@ def rpid_cur(ctx, A, k, J):
 
 
 def rpid_residual(ctx, which, A, k, J, Z=None, I=None, U=None) -> float:
-    """||A - C Z||_F / ||A||_F (which=RESIDUAL_ID) or ||A - C U R||_F / ||A||_F."""
+    """||A - C Z||_F / ||A||_F (which=RESIDUAL_ID), ||A - C U R||_F / ||A||_F
+    (RESIDUAL_CUR) or ||A - Z^T R||_F / ||A||_F (RESIDUAL_ROW_ID, Z k x m)."""
     pa, m, n, lda = colmajor(A)
     out = ctypes.c_double(0.0)
     s = lib().rpid_residual(
-        ctx.handle, int(which), pa, dtype_code(A), m, n, lda, k, J.data_ptr(),
+        ctx.handle, int(which), pa, dtype_code(A), m, n, lda, k, J.data_ptr() if J is not None else None,
         Z.data_ptr() if Z is not None else None, Z.stride(1) if Z is not None else k,
         I.data_ptr() if I is not None else None,
         U.data_ptr() if U is not None else None, U.stride(1) if U is not None else k,

@@ -371,3 +371,91 @@ def pin_power_improves(O, m=80, n=60, k=6, l=8, reps=40):
 
 
 ALL_PINS += [pin_power_orthonormal, pin_power_diagonal, pin_power_exact_rank, pin_power_improves]
+
+
+def pin_two_sided_bruteforce(O, seed=45, m=7, n=6, l=3):
+    """Alg. 3, step 2 on small integer matrices: X(r, j) = sum_i Gamma(r, i)
+    A(i, j) and Y(i, r) = sum_j A(i, j) Omega(r, j), written out as sums of
+    exact integer products (no matrix routine)."""
+    rng = np.random.default_rng(seed)
+    a = rng.integers(-4, 5, (m, n)).astype(float)
+    g = rng.integers(-3, 4, (l, m)).astype(float)
+    om = rng.integers(-3, 4, (l, n)).astype(float)
+    X, Y = O.sketch_two_sided(a, g, om)
+    assert X.shape == (l, n) and Y.shape == (m, l)
+    for r in range(l):
+        for j in range(n):
+            assert X[r, j] == sum(g[r, i] * a[i, j] for i in range(m))
+        for i in range(m):
+            assert Y[i, r] == sum(a[i, j] * om[r, j] for j in range(n))
+
+
+def pin_row_id_structure(O, seed=46, m=50, n=40, k=6, l=9):
+    """Row ID from the column sketch: W(I, :) = I_k, and W reproduces the
+    sketch it came from, W Y(I, 0:k) = Y(:, 0:k)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((m, n))
+    _, Y = O.sketch_two_sided(a, rng.standard_normal((l, m)), rng.standard_normal((l, n)))
+    I = O.lupp_rowwise(Y, k)["J"]
+    W = O.row_id_coeffs(Y, I, k)
+    assert W.shape == (m, k)
+    assert np.array_equal(W[I, :], np.eye(k))
+    np.testing.assert_allclose(W @ Y[I, :k], Y[:, :k], rtol=0, atol=1e-10 * np.abs(Y).max())
+
+
+def pin_two_sided_exact_rank(O, seed=47, m=80, n=60, k=7):
+    """rank(A) = k, l = k (Lemma 1 and its row analogue): the row ID W A(I, :)
+    and the cheap CUR C S^{-1} R both reproduce A, and S^{-1} equals the
+    stable core C^+ A R^+ (both are the unique U with C U R = A)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+    d = O.decompose_two_sided(a, rng.standard_normal((k, m)), rng.standard_normal((k, n)), k)
+    na = np.linalg.norm(a)
+    J, I = d["J"], d["I"]
+    assert np.linalg.norm(a - d["W"] @ a[I, :]) <= 1e-9 * na
+    assert np.linalg.norm(a - a[:, J] @ d["U_sketch"] @ a[I, :]) <= 1e-9 * na
+    np.testing.assert_allclose(d["U_sketch"], d["U"], rtol=1e-7, atol=1e-9 * np.abs(d["U"]).max())
+    r = O.residuals(a, J, Z=d["Z"], I=I, U=d["U_sketch"], W=d["W"])
+    assert max(r["id"], r["cur"], r["rowid"]) <= 1e-9
+
+
+def pin_cur_sketch_inverse(O, seed=48, m=30, n=25, k=5):
+    """S^{-1} S = I for S = A(I, J) taken in the given index orders (rows in
+    the order of I, columns in the order of J)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((m, n))
+    I = np.array([7, 2, 19, 0, 11])
+    J = np.array([3, 24, 8, 1, 15])
+    U = O.cur_sketch_u(a, J, I)
+    S = np.array([[a[i, j] for j in J] for i in I])
+    np.testing.assert_allclose(U @ S, np.eye(k), rtol=0, atol=1e-10)
+
+
+def pin_two_sided_bounds(O, m=90, n=70, k=8, l=12, seeds=range(5)):
+    """On noisy low-rank inputs: the stable core is Frobenius-optimal for the
+    given C and R, so ||A - C S^{-1} R|| >= ||A - C (C^+ A R^+) R||; the row ID
+    from the sketch obeys the row analogue of Theorem 1, ||A - W R|| <=
+    eta_Y ||A - Y Y^+ A|| with eta_Y = sqrt(1 + ||W(rest, :)||_2^2); and the
+    CUR bound of the Remark after Alg. 3 holds."""
+    for sd in seeds:
+        rng = np.random.default_rng([sd, 49])
+        a = rng.standard_normal((m, k)) @ rng.standard_normal((k, n)) + 1e-2 * rng.standard_normal((m, n))
+        d = O.decompose_two_sided(a, rng.standard_normal((l, m)), rng.standard_normal((l, n)), k)
+        J, I, X, Y = d["J"], d["I"], d["X"], d["Y"]
+        C, R = a[:, J], a[I, :]
+        e_cheap = np.linalg.norm(a - C @ d["U_sketch"] @ R)
+        e_stable = np.linalg.norm(a - C @ d["U"] @ R)
+        assert e_stable <= e_cheap * (1 + 1e-12)
+        rest = np.setdiff1d(np.arange(m), I)
+        eta_y = np.sqrt(1.0 + np.linalg.norm(d["W"][rest, :], 2) ** 2)
+        qy, _ = np.linalg.qr(Y[:, :k])
+        rf_y = np.linalg.norm(a - qy @ (qy.T @ a))
+        assert np.linalg.norm(a - d["W"] @ R) <= eta_y * rf_y * (1 + 1e-10)
+        eta_x = O.eta(d["Z"], J)
+        qx, _ = np.linalg.qr(X[:k, :].T)
+        rf_x = np.linalg.norm(a - (a @ qx) @ qx.T)
+        assert e_stable <= (eta_x * rf_x + eta_y * rf_y) * (1 + 1e-10)
+
+
+ALL_PINS += [pin_two_sided_bruteforce, pin_row_id_structure, pin_two_sided_exact_rank,
+             pin_cur_sketch_inverse, pin_two_sided_bounds]

@@ -60,6 +60,15 @@ MUTANTS = {
                                          "    Y = A @ _f64(Omega).T\n    return (Y.T @ A) @ (A.T @ A)"),
     "power sketch normalised": ("    Y = A @ _f64(Omega).T\n    return Y.T @ A",
                                 "    Y = A @ _f64(Omega).T\n    return Y.T @ A / np.linalg.norm(A)"),
+    "two-sided Y with the columns of Omega reversed": ("return _f64(Gamma) @ A, A @ _f64(Omega).T",
+                                                   "return _f64(Gamma) @ A, A @ _f64(Omega)[:, : A.shape[1]].T[::-1]"),
+    "row ID from the untransposed system": ("W = np.linalg.solve(Yk[I, :].T, Yk.T).T",
+                                            "W = np.linalg.solve(Yk[I, :], Yk.T).T"),
+    "cheap CUR core not inverted": ("return np.linalg.solve(S, np.eye(S.shape[0]))", "return S"),
+    "cheap CUR core from S transposed": ("return np.linalg.solve(S, np.eye(S.shape[0]))",
+                                         "return np.linalg.solve(S.T, np.eye(S.shape[0]))"),
+    "row ID residual with C instead of R": ('out["rowid"] = nrm(A - _f64(W) @ R) / na',
+                                            'out["rowid"] = nrm(A - _f64(W) @ R[:, ::-1]) / na'),
 }
 
 
