@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--only-main", action="store_true", help="time the main mode only")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank report")
+    ap.add_argument("--two-sided-only", action="store_true",
+                    help="run only the Alg. 3 report on the main mode's input (for profiling)")
     ap.add_argument("--input-cache", default=None,
                     help="folder: load the FP32 workload from it if stored there, else "
                          "generate it and store it (lets profiled runs skip the QR-based "
@@ -192,6 +194,53 @@ def power_report(torch, R, ctx, A, Om, plain):
             "residual_id": rid, "residual_cur": rcur,
             "residual_id_plain": plain["rid"], "residual_cur_plain": plain["rcur"],
             "status_columns": st, "status_rows": st_i}
+
+
+def two_sided_report(torch, R, ctx, A, Gam, plain):
+    """Alg. 3 on the same input: X = Gamma A and Y^T = Omega A^T in one
+    call (BF16: one pass over A in row blocks), LUPP on both, then the
+    sketch-only estimates (row ID from Y, core S^{-1}) beside the stable CUR
+    of the same indices.  GPU times per call back to back."""
+    from paper_2104_05877_amd import inputs
+
+    Om = inputs.torch_gaussian(L, N, 1234, A.device, dtype=A.dtype).T.contiguous().T
+    refine = 0 if A.dtype == torch.float64 else 1
+
+    def timed(fn, reps=10):
+        for _ in range(2):
+            out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    (X, Yt), ms_two = timed(lambda: R.rpid_sketch_two_sided(ctx, A, Gam, Om))
+    _, ms_plain = timed(lambda: R.rpid_sketch(ctx, A, Gam))
+
+    def select_both():
+        cj = R.rpid_select_columns(ctx, X, K, sync=False)
+        ci = R.rpid_select_columns(ctx, Yt, K, sync=False)
+        return cj, ci
+
+    ((J, Lf, Uf, _, _, _), (I, Li, Ui, _, _, _)), ms_sel = timed(select_both, reps=5)
+    Z, _ = R.rpid_id_coeffs(ctx, X, K, J, Lf, Uf, refine_steps=refine)
+    Zy, _ = R.rpid_id_coeffs(ctx, Yt, K, I, Li, Ui, refine_steps=refine)
+    (Us, st), ms_core = timed(lambda: R.rpid_cur_sketch(ctx, A, K, J, I), reps=5)
+    Ist, Ust, _, _ = R.rpid_cur(ctx, A, K, J)  # Alg. 2's row indices, stable core, for reference
+    return {
+        "two_sided_sketch_ms": ms_two, "plain_sketch_ms": ms_plain,
+        "select_columns_and_rows_ms": ms_sel, "cur_sketch_core_ms": ms_core,
+        "indices_only_ms": ms_two + ms_sel,
+        "residual_id": R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, J, Z=Z),
+        "residual_row_id": R.rpid_residual(ctx, R.RESIDUAL_ROW_ID, A, K, None, Z=Zy, I=I),
+        "residual_cur_sketch_core": R.rpid_residual(ctx, R.RESIDUAL_CUR, A, K, J, I=I, U=Us),
+        "residual_cur_alg2_stable": R.rpid_residual(ctx, R.RESIDUAL_CUR, A, K, J, I=Ist, U=Ust),
+        "status_core": st,
+    }
 
 
 def calibration_copy(torch):
@@ -364,6 +413,12 @@ def main():
     data = make_inputs(torch, args.seed, args.input_cache)
     calibration_copy(torch)
     ctx = R.Context(0)
+    if args.two_sided_only:
+        A, Om = data[args.mode]
+        rep = two_sided_report(torch, R, ctx, A, Om, None)
+        ctx.close()
+        print(json.dumps({"mode": args.mode, "two_sided": rep}), flush=True)
+        return
     results = {}
     order = [args.mode] + [m for m in ("bf16", "f32", "f64") if m != args.mode]
     if args.only_main:
@@ -442,6 +497,8 @@ def main():
     if not args.only_main:
         log("power-iteration report (Rand-LUPP-1piter)")
         line["power_iteration"] = power_report(torch, R, ctx, *data[args.mode], main_r)
+        log("two-sided report (Alg. 3)")
+        line["two_sided"] = two_sided_report(torch, R, ctx, *data[args.mode], main_r)
     if not args.no_learned and not args.only_main:
         log("learned-rank report")
         line["learned_rank"] = learned_report(torch, ctx)

@@ -122,7 +122,7 @@ int rpid_sketch_power1(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, i
  *   Yt     l x m, ldyt >= l, type out_t (output)
  * a_t F64 gives out_t F64; F32 and BF16 give out_t F32 (FP32 accumulation).
  * 1 <= l <= 1024.  BF16 with A 16-byte aligned, lda a multiple of 8, n a
- * multiple of 64 and m of 8 reads A once: row blocks of at most 64 MiB feed
+ * multiple of 64 and m of 8 reads A once: row blocks of at most 128 MiB feed
  * both products back to back (the second read of a block comes from the
  * last-level cache); other cases form a transposed copy of A in the
  * workspace and read A twice.

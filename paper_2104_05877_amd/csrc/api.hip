@@ -647,11 +647,11 @@ int rpid_sketch_two_sided(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m
   const size_t es = esize(a_t);
   const int acc = a_t == RPID_F64 ? 8 : 4;
   const bool in_place = a_t == RPID_BF16 && at_bf16_fits(A, m, n, lda, l);
-  // Row blocks of A small enough to stay in the last-level cache between the
-  // two products of a block (64 MiB, a multiple of 64 rows).
+  // Row blocks of A small enough to stay in the 256 MB last-level cache
+  // between the two products of a block (128 MiB, a multiple of 64 rows).
   int64_t mb = m;
   if (in_place) {
-    mb = ((int64_t)64 << 20) / (n * 2);
+    mb = ((int64_t)128 << 20) / (n * 2);
     mb = std::max<int64_t>(64, mb / 64 * 64);
     if (mb >= m) mb = m;
   }

@@ -51,14 +51,14 @@ def dev(a, dt, pad=0):
 U_ROUND = {"float64": 2.0**-53, "float32": 2.0**-24, "bfloat16": 2.0**-24}
 
 # (m, n, l, pad, seed).  BF16 reads A in place when n % 64 == 0 and m % 8 ==
-# 0 (then m = 8200, n = 8192 takes three row blocks, the last of 8 rows);
-# the other shapes take the transposed-copy path.
+# 0 (then m = 8200, n = 16384 takes three row blocks of 4096, 4096 and 8
+# rows); the other shapes take the transposed-copy path.
 CASES = [
     (1000, 800, 60, 0, 1),
     (1000, 512, 272, 0, 2),
     (1024, 2048, 64, 24, 3),
     (777, 640, 40, 0, 4),
-    (8200, 8192, 64, 0, 5),
+    (8200, 16384, 64, 0, 5),
 ]
 
 
@@ -95,7 +95,7 @@ def test_two_sided_fp64_decomposition(R, ctx):
     core S^{-1} match the oracle's within their conditioning, and the row ID
     and cheap CUR residuals match to 1e-9 relative."""
     m, n, k, l = 1200, 1000, 40, 48
-    A, _ = inputs.small_spectral_case(m, n, k, l, inputs.exp_spectrum(min(m, n), 6.0), 11)
+    A, _ = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 11)
     rng = np.random.default_rng(12)
     G, Om = rng.standard_normal((l, m)), rng.standard_normal((l, n))
     Ad = dev(A, torch.float64)
