@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--only-main", action="store_true", help="time the main mode only")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank report")
     ap.add_argument("--two-sided-only", action="store_true",
-                    help="run only the Alg. 3 report on the main mode's input (for profiling)")
+                    help="run only the Alg. 3 and Rand-CPQR reports on the main mode's input (for profiling)")
     ap.add_argument("--input-cache", default=None,
                     help="folder: load the FP32 workload from it if stored there, else "
                          "generate it and store it (lets profiled runs skip the QR-based "
@@ -243,6 +243,34 @@ def two_sided_report(torch, R, ctx, A, Gam, plain):
     }
 
 
+def cpqr_report(torch, R, ctx, A, Om, plain):
+    """Rand-CPQR on the same sketch as Rand-LUPP (the paper's comparison):
+    GPU time of the column-pivoted QR (k steps) and of its Z, and the ID
+    residual of its pivots beside Rand-LUPP's."""
+    X = R.rpid_sketch(ctx, A, Om)
+
+    def timed(fn, reps=5):
+        out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    (J, Rf, diag, _, _), ms_qr = timed(lambda: R.rpid_select_columns_cpqr(ctx, X, K, sync=False))
+    Z, ms_z = timed(lambda: R.rpid_id_coeffs_cpqr(ctx, K, J, Rf))
+    rid = R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, J, Z=Z)
+    out = {"cpqr_ms": ms_qr, "cpqr_us_per_pivot": ms_qr * 1e3 / K, "id_coeffs_cpqr_ms": ms_z,
+           "residual_id_cpqr": rid}
+    if plain is not None:
+        out.update({"lupp_select_columns_ms": plain["per_call_ms"]["select_columns"],
+                    "lupp_id_coeffs_ms": plain["per_call_ms"]["id_coeffs"], "residual_id_lupp": plain["rid"]})
+    return out
+
+
 def calibration_copy(torch):
     """One elementwise kernel that reads CALIB_MIB MiB and writes CALIB_MIB MiB
     (a negating copy: a plain same-dtype copy would go to the DMA engines),
@@ -416,8 +444,9 @@ def main():
     if args.two_sided_only:
         A, Om = data[args.mode]
         rep = two_sided_report(torch, R, ctx, A, Om, None)
+        rep_qr = cpqr_report(torch, R, ctx, A, Om, None)
         ctx.close()
-        print(json.dumps({"mode": args.mode, "two_sided": rep}), flush=True)
+        print(json.dumps({"mode": args.mode, "two_sided": rep, "cpqr": rep_qr}), flush=True)
         return
     results = {}
     order = [args.mode] + [m for m in ("bf16", "f32", "f64") if m != args.mode]
@@ -499,6 +528,8 @@ def main():
         line["power_iteration"] = power_report(torch, R, ctx, *data[args.mode], main_r)
         log("two-sided report (Alg. 3)")
         line["two_sided"] = two_sided_report(torch, R, ctx, *data[args.mode], main_r)
+        log("Rand-CPQR report")
+        line["cpqr"] = cpqr_report(torch, R, ctx, *data[args.mode], main_r)
     if not args.no_learned and not args.only_main:
         log("learned-rank report")
         line["learned_rank"] = learned_report(torch, ctx)

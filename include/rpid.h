@@ -186,6 +186,40 @@ int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, 
                         int64_t ldu, void* diagU, int64_t* k_eff);
 
 /*
+ * Rand-CPQR skeleton selection on the same sketch (the comparison pivoting
+ * of Sec. 5; column-pivoted QR of eq. def_QRCP): k steps of Householder QR
+ * with column pivoting on X.  Step t picks the remaining column with the
+ * largest norm of its rows t..l-1 (ties to the smallest column), reflects it
+ * to alpha e_t with alpha = -sign(x_t) ||x(t:l)||, and applies the reflector
+ * to every remaining column; column norms are recomputed at every step.
+ *   X, x_t (F64 or F32), l, n, ldx as for rpid_select_columns; 1 <= l <= 512,
+ *   k <= min(l, n), n <= 32 x (compute units) (8192 on MI355X)
+ *   J      int64[k]   pivots in pivot order (0-based columns of X)
+ *   Rf     k x n, ldr >= k, type x_t: rows 0..k-1 of R in the original column
+ *          order (Rf(t, J[t]) = alpha_t, Rf(t, J[s]) = 0 for s < t), so
+ *          that X(:, J) = Q Rf(:, J) with orthonormal Q
+ *   diagR  k values of type x_t: |Rf(t, J[t])|; may be NULL
+ *   k_eff  host int64*, NULL to skip the synchronising status read
+ * Returns 0, t + 1 when every remaining column is exactly zero in rows t..
+ * (k_eff = t), RPID_ERR_NONFINITE for NaN/Inf in X, RPID_ERR_UNSUPPORTED for
+ * sizes outside the limits above.
+ */
+int rpid_select_columns_cpqr(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                             int64_t ldx, int64_t k, int64_t* J, void* Rf, int64_t ldr, void* diagR,
+                             int64_t* k_eff);
+
+/*
+ * ID coefficients from the column-pivoted QR of the sketch: Z = R11^{-1} Rf
+ * with R11 = Rf(:, J) (upper triangular in pivot order), so that Z(:, J) = I
+ * and Z = X(:, J)^+ X (Sec. 4's estimate of C^+ A with all l rows).
+ *   r_t    type of Rf (F64 or F32); k, n, J, Rf, ldr as returned by
+ *          rpid_select_columns_cpqr
+ *   Z      k x n FP64, ldz >= k (output)
+ */
+int rpid_id_coeffs_cpqr(rpid_ctx ctx, rpid_dtype r_t, int64_t k, int64_t n, const int64_t* J,
+                        const void* Rf, int64_t ldr, double* Z, int64_t ldz);
+
+/*
  * S4 -- ID coefficients from the pivoted sketch (Sec. 4: C^+ A ~ X_1^+ X):
  * Z = X_1^{-1} X_k with X_k = X(0:k, :), X_1 = X_k(:, J), so that A ~ A(:, J) Z.
  * Computed from the LUPP factors: Z(:, J[t]) = e_t and, for j not in J,

@@ -31,6 +31,9 @@ randomized pivoting algorithms for CUR and interpolative decompositions":
 * cur_sketch_u      -- the CUR core S^{-1}, S = A(I_s, J_s), that needs no
                        further pass over A (after Alg. 3).
 * decompose_two_sided -- Alg. 3 end to end with the estimates above.
+* cpqr_colwise      -- column-pivoted Householder QR of the sketch, eq.
+                       (def_QRCP): the pivoting of Rand-CPQR (Sec. 5).
+* id_coeffs_cpqr    -- Z = R_11^{-1} R_top from that QR (Z = X_1^+ X).
 
 Everything is float64 numpy.  Library primitives used as single steps: matmul,
 QR, triangular/linear solves, SVD (for spectral norms only).
@@ -68,6 +71,8 @@ __all__ = [
     "row_id_coeffs",
     "cur_sketch_u",
     "decompose_two_sided",
+    "cpqr_colwise",
+    "id_coeffs_cpqr",
     "NonFiniteInput",
 ]
 
@@ -425,3 +430,74 @@ def decompose_two_sided(A, Gamma, Omega, k, gaps=False):
     out["U_sketch"] = cur_sketch_u(A, col["J"], row["J"])
     out["U"] = cur_u(A, col["J"], row["J"])
     return out
+
+
+# --------------------------------------------------------------------------
+# Rand-CPQR (Sec. 5): column-pivoted QR, eq. (def_QRCP), on the same sketch
+# --------------------------------------------------------------------------
+def cpqr_colwise(X, k, gaps=False):
+    """k steps of Householder QR with column pivoting on X (l x n).
+
+    At step t the pivot is the remaining column whose rows t..l-1 (of the
+    matrix updated by the earlier reflectors) have the largest Euclidean norm,
+    ties to the smallest column; the norms are computed afresh at every step.
+    The reflector of the pivot column w = X^(t)(t:, p) maps it to alpha e_0
+    with alpha = -sign(w_0) ||w|| (sign(0) = +1): v = w - alpha e_0,
+    beta = 1 / (alpha (alpha - w_0)), and every remaining column x gets
+    x(t:) -= beta (v^T x(t:)) v.  Row t of R is row t after that update.
+
+    Returns a dict with J (pivots in order), R (k x n, original column order;
+    R[t, J[t]] = alpha_t, zero at the earlier pivots), diag = |alpha_t|,
+    k_eff, status (t + 1 when every remaining column is zero in rows t..)
+    and, with gaps=True, the relative gap between the two largest norms at
+    each step.
+    """
+    S = _f64(X).copy()
+    if not np.all(np.isfinite(S)):
+        raise NonFiniteInput("non-finite entry in the sketch")
+    l, n = S.shape
+    remaining = np.ones(n, dtype=bool)
+    R = np.zeros((k, n))
+    J, gap = [], []
+    status = 0
+    for t in range(k):
+        norms = np.sqrt(np.sum(S[t:, :] ** 2, axis=0))
+        cand = np.where(remaining, norms, -1.0)
+        p = int(cand.argmax())  # the first maximum
+        if not cand[p] > 0.0:
+            status = t + 1
+            break
+        if gaps:
+            others = np.delete(cand, p)
+            second = others.max() if others.size else -1.0
+            gap.append((cand[p] - max(second, 0.0)) / cand[p])
+        w = S[t:, p].copy()
+        alpha = -np.linalg.norm(w) if w[0] >= 0.0 else np.linalg.norm(w)
+        v = w.copy()
+        v[0] -= alpha
+        beta = 1.0 / (alpha * (alpha - w[0]))
+        cols = remaining.copy()
+        cols[p] = False
+        d = v @ S[t:, cols]
+        S[t:, cols] -= beta * np.outer(v, d)
+        R[t, cols] = S[t, cols]
+        R[t, p] = alpha
+        S[t:, p] = 0.0
+        remaining[p] = False
+        J.append(p)
+    out = dict(J=np.array(J, dtype=np.int64), R=R, diag=np.abs(np.array([R[t, J[t]] for t in range(len(J))])),
+               k_eff=len(J), status=status)
+    if gaps:
+        out["gap"] = np.array(gap)
+    return out
+
+
+def id_coeffs_cpqr(R, J):
+    """Z = R_11^{-1} R with R_11 = R(:, J): the ID coefficients of the
+    column-pivoted QR (equal to X(:, J)^+ X for the sketch X)."""
+    R = _f64(R)
+    J = np.asarray(J, dtype=np.int64)
+    k = J.shape[0]
+    Z = sla.solve_triangular(R[:k, J], R[:k, :], lower=False)
+    Z[:, J] = np.eye(k)
+    return Z

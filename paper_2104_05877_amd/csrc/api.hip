@@ -812,6 +812,78 @@ int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, 
 }
 
 // ---------------------------------------------------------------------------
+int rpid_select_columns_cpqr(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                             int64_t ldx, int64_t k, int64_t* J, void* Rf, int64_t ldr, void* diagR,
+                             int64_t* k_eff) {
+  if (!ctx) return -1;
+  if (!X) return -2;
+  if (!is_lupp_type(x_t)) return -3;
+  if (l < 1 || l > 512) return -4;
+  if (n < 1) return -5;
+  if (ldx < l) return -6;
+  if (k < 1 || k > l || k > n) return -7;
+  if (!J) return -8;
+  if (!Rf) return -9;
+  if (ldr < k) return -10;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_status = cv.take<int64_t>(8);
+  RPID_CHECK(ensure_workspace(ctx, cv.off));
+  int64_t* status_dev = ws_ptr<int64_t>(ctx, o_status);
+  int s;
+  if (x_t == RPID_F64)
+    s = cpqr_panel<double>(ctx, (const double*)X, ldx, 1, n, l, k, J, (double*)Rf, ldr, (double*)diagR,
+                           status_dev);
+  else
+    s = cpqr_panel<float>(ctx, (const float*)X, ldx, 1, n, l, k, J, (float*)Rf, ldr, (float*)diagR,
+                          status_dev);
+  if (s != RPID_OK) return s;
+  if (!k_eff) return RPID_OK;
+  int64_t st = 0;
+  RPID_CHECK(read_status(ctx, status_dev, &st));
+  if (st < 0) return (int)st;
+  *k_eff = (st == 0) ? k : st - 1;
+  return (int)st;
+}
+
+int rpid_id_coeffs_cpqr(rpid_ctx ctx, rpid_dtype r_t, int64_t k, int64_t n, const int64_t* J,
+                        const void* Rf, int64_t ldr, double* Z, int64_t ldz) {
+  if (!ctx) return -1;
+  if (!is_lupp_type(r_t)) return -2;
+  if (k < 1 || k > 1024) return -3;
+  if (n < k) return -4;
+  if (!J) return -5;
+  if (!Rf) return -6;
+  if (ldr < k) return -7;
+  if (!Z) return -8;
+  if (ldz < k) return -9;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_R11 = cv.take<double>((size_t)k * k);
+  const size_t o_W = cv.take<double>((size_t)k * k);
+  const size_t o_R64 = r_t == RPID_F64 ? 0 : cv.take<double>((size_t)k * n);
+  const size_t o_tmp = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, o_tmp + (size_t)64 * k * k * sizeof(double) + 4096));
+  double* R11 = ws_ptr<double>(ctx, o_R11);
+  double* Wi = ws_ptr<double>(ctx, o_W);
+  const double* R64 = (const double*)Rf;
+  int64_t ld64 = ldr;
+  if (r_t == RPID_F64) {
+    RPID_CHECK(gather_columns<double, double>(ctx, k, k, (const double*)Rf, ldr, n, J, R11, k));
+  } else {
+    double* Rc = ws_ptr<double>(ctx, o_R64);
+    RPID_CHECK(convert_matrix<float, double>(ctx, k, n, (const float*)Rf, ldr, Rc, k));
+    RPID_CHECK(gather_columns<double, double>(ctx, k, k, Rc, k, n, J, R11, k));
+    R64 = Rc;
+    ld64 = k;
+  }
+  // Z = R11^{-1} R_top, with R11 = R_top(:, J) upper triangular in pivot order
+  RPID_CHECK(tri_inverse(ctx, k, R11, k, false, false, Wi, k, o_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, k, n, k, 1.0, Wi, k, R64, ld64, 0.0, Z, ldz, o_tmp));
+  return set_identity_columns(ctx, k, J, Z, ldz);
+}
+
+// ---------------------------------------------------------------------------
 int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
                    int64_t ldx, int64_t k, const int64_t* J, const void* Lf, int64_t ldl,
                    const void* Uf, int64_t ldu, double* Z, int64_t ldz, int refine_steps,

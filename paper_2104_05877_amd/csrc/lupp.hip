@@ -511,6 +511,30 @@ static int dispatch_R(rpid_ctx ctx, LuppArgs<T> a, int R, int G, int nt) {
   }
 }
 
+// The context's uncached exchange buffer, grown to `bytes` if needed (the
+// old one is left allocated on purpose), and a fresh launch epoch for the
+// tags; the buffer is cleared when it is new or the epoch wraps.
+static int exchange_buffer(rpid_ctx ctx, size_t bytes, char** base, unsigned* epoch) {
+  bool fresh = false;
+  if (bytes > ctx->uc_bytes) {
+    size_t want = bytes < ((size_t)4 << 20) ? ((size_t)4 << 20) : bytes;
+    void* p = nullptr;
+    if (hipExtMallocWithFlags(&p, want, hipDeviceMallocUncached) != hipSuccess) return RPID_ERR_NOMEM;
+    ctx->uc = p;
+    ctx->uc_bytes = want;
+    fresh = true;
+  }
+  // launch epoch (21 bits) tags every exchanged word; tag 0 never matches
+  if (++ctx->lupp_epoch >= (1u << 21)) {
+    ctx->lupp_epoch = 1;
+    fresh = true;
+  }
+  if (fresh) RPID_CHECK(launch_fill_u64(ctx, static_cast<uint64_t*>(ctx->uc), ctx->uc_bytes / 8, 0ull));
+  *base = static_cast<char*>(ctx->uc);
+  *epoch = ctx->lupp_epoch;
+  return RPID_OK;
+}
+
 template <typename T>
 int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, int64_t k,
                int64_t* J, T* Lf, int64_t ldl, T* Uf, int64_t ldu, T* diag, size_t ws_off,
@@ -562,24 +586,9 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   const size_t o_val = cv.take<uint64_t>((size_t)kValRep * xrep);
   const size_t o_row = cv.take<uint64_t>((size_t)2 * G * xstride * W);
   const size_t o_flag = cv.take<uint64_t>(1);
-  bool fresh = false;
-  if (cv.off > ctx->uc_bytes) {
-    // the previous buffer (if any) is left allocated on purpose
-    size_t want = cv.off < ((size_t)4 << 20) ? ((size_t)4 << 20) : cv.off;
-    void* p = nullptr;
-    if (hipExtMallocWithFlags(&p, want, hipDeviceMallocUncached) != hipSuccess) return RPID_ERR_NOMEM;
-    ctx->uc = p;
-    ctx->uc_bytes = want;
-    fresh = true;
-  }
-  // launch epoch (21 bits) tags every exchanged word; tag 0 never matches
-  if (++ctx->lupp_epoch >= (1u << 21)) {
-    ctx->lupp_epoch = 1;
-    fresh = true;
-  }
-  if (fresh)
-    RPID_CHECK(launch_fill_u64(ctx, static_cast<uint64_t*>(ctx->uc), ctx->uc_bytes / 8, 0ull));
-  char* ucb = static_cast<char*>(ctx->uc);
+  char* ucb = nullptr;
+  unsigned epoch = 0;
+  RPID_CHECK(exchange_buffer(ctx, cv.off, &ucb, &epoch));
 
   LuppArgs<T> a;
   a.base = base;
@@ -598,7 +607,7 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
   a.xrep = xrep;
   a.xrow = reinterpret_cast<uint64_t*>(ucb + o_row);
   a.xflag = reinterpret_cast<uint64_t*>(ucb + o_flag);
-  a.epoch = ctx->lupp_epoch;
+  a.epoch = epoch;
   a.status = status_dev;
   if (H == 1) {
     if (ntmax == 256) return dispatch_R<T, 256, 1>(ctx, a, R, G, nt);
@@ -616,5 +625,391 @@ template int lupp_panel<double>(rpid_ctx, const double*, int64_t, int64_t, int64
 template int lupp_panel<float>(rpid_ctx, const float*, int64_t, int64_t, int64_t, int64_t,
                                int64_t*, float*, int64_t, float*, int64_t, float*, size_t,
                                int64_t*);
+
+// ---------------------------------------------------------------------------
+// Column-pivoted Householder QR of a sketch X (l x n), k steps, as one
+// persistent cooperative kernel (the CPQR of eq. def_QRCP, applied to the
+// sketch as in Rand-CPQR).
+//
+// Panel P(i, j) = base[i * rs + j * cs] = X(j, i): i = column of X (the
+// candidate), j = row of X.  Workgroup g owns candidates [g R, g R + R);
+// thread j (< l) holds P(i, j) of them in R registers.
+// Step t: pivot p_t = the remaining column with the largest norm of its
+// rows t..l-1 (ties to the smallest column); Householder reflector from the
+// pivot column, w = X(t:l, p_t): alpha = -sign(w_0) ||w||, v = w - alpha e_0,
+// H = I - beta v v^T with beta = 1 / (alpha (alpha - w_0)); every remaining
+// column gets x <- x - beta (v^T x) v.  Row t of R is the updated row t
+// (R(t, p_t) = alpha); the column norms of rows t+1.. are recomputed from the
+// updated values (no downdating).
+// Exchange per step as in the LUPP kernel: a tagged candidate value (the
+// squared norm) in kValRep copies, the candidate column as tagged words,
+// one wave per workgroup polls and reduces the values identically.  Every
+// workgroup builds alpha and beta from the same fetched words in the same
+// order, so all of them apply bit-identical reflectors.
+// Sums over the l rows of a column (the dot products v^T x and the norms)
+// are workgroup reductions of R values at once: within a wave, halving
+// exchanges leave lane pair (2q, 2q+1) (R = 32) with the wave's sum for
+// candidate q, then the per-wave sums are added in wave order.
+template <typename T>
+struct CpqrArgs {
+  const T* base;
+  int64_t rs, cs;
+  int64_t n;
+  int l, lpad, k;
+  int64_t* J;
+  T* Rf;
+  int64_t ldr;
+  T* diag;
+  uint64_t* xval;
+  int64_t xrep;
+  uint64_t* xrow;
+  uint64_t* xflag;
+  unsigned epoch;
+  int64_t* status;
+};
+
+// One halving exchange of wave_rowsum: C values per lane become C / 2, the
+// lane keeping the upper half when its bit O is set (O = 32 C / R), and the
+// next exchange follows.  Recursion keeps every register index a constant.
+template <typename T, int C, int R>
+struct RowsumHalve {
+  static __device__ __forceinline__ void run(T* v, int lane) {
+    constexpr int H = C / 2;
+    constexpr int O = 32 * C / R;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const T send = up ? v[i] : v[H + i];
+      const T keep = up ? v[H + i] : v[i];
+      v[i] = keep + __shfl_xor(send, O, 64);
+    }
+    RowsumHalve<T, H, R>::run(v, lane);
+  }
+};
+template <typename T, int R>
+struct RowsumHalve<T, 1, R> {
+  static __device__ __forceinline__ void run(T*, int) {}
+};
+
+// Sum over the 64 lanes of a wave for each of R values per lane; the result
+// for value q ends in lanes q * (64 / R) .. (q + 1) * (64 / R) - 1.
+template <typename T, int R>
+__device__ __forceinline__ T wave_rowsum(T (&v)[R], int lane) {
+  static_assert(R >= 1 && R <= 64 && (R & (R - 1)) == 0, "R a power of two <= 64");
+  RowsumHalve<T, R, R>::run(v, lane);
+#pragma unroll
+  for (int o = 32 / R; o >= 1; o /= 2) v[0] += __shfl_xor(v[0], o, 64);
+  return v[0];
+}
+
+template <typename T, int R, int NTMAX>
+__global__ __launch_bounds__(NTMAX) void cpqr_panel_kernel(CpqrArgs<T> a) {
+  constexpr int W = Words<T>::W;
+  constexpr int NW = NTMAX / 64;
+  const int tid = threadIdx.x;
+  const int nwav = blockDim.x / 64;
+  const int g = blockIdx.x;
+  const int G = gridDim.x;
+  const int l = a.l, k = a.k;
+  const int j = tid;  // row of X held by this thread
+  const int64_t row0 = (int64_t)g * R;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+
+  __shared__ T part[NW][R];
+  __shared__ T nrm[R];
+  __shared__ T dsum[R];
+  __shared__ int alive[R];
+  __shared__ T wpart[NW];
+  __shared__ T sh_w0;
+  __shared__ int sh_bq, sh_gw, sh_code, sh_abort, sh_bad;
+  __shared__ T sh_best;
+  __shared__ int64_t sh_status;
+
+  T s[R];
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int64_t col = row0 + q;
+    T v = T(0);
+    if (col < a.n && j < l) v = a.base[col * a.rs + (int64_t)j * a.cs];
+    bad |= !isfinite(v);
+    s[q] = v;
+  }
+  for (int q = tid; q < R; q += blockDim.x) alive[q] = (row0 + q < a.n) ? 1 : 0;
+  if (tid == 0) {
+    sh_abort = 0;
+    sh_bad = 0;
+  }
+  __syncthreads();
+  if (__any(bad) && lane == 0) sh_bad = 1;
+
+  // out[q] = sum over the threads of vals[q] (wave sums added in wave order)
+  auto block_rowsum = [&](T (&vals)[R], T* out) {
+    const T ws = wave_rowsum<T, R>(vals, lane);
+    if ((lane & (64 / R - 1)) == 0) part[wid][lane / (64 / R)] = ws;
+    __syncthreads();
+    if (tid < R) {
+      T acc = part[0][tid];
+      for (int w = 1; w < nwav; ++w) acc += part[w][tid];
+      out[tid] = acc;
+    }
+    __syncthreads();
+  };
+  // squared norms of rows t.. of every owned column, and the candidate
+  auto norms_and_candidate = [&](int t) {
+    T vals[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) vals[q] = (j >= t && j < l) ? s[q] * s[q] : T(0);
+    block_rowsum(vals, nrm);
+    if (wid == 0) {
+      T v = (lane < R && alive[lane]) ? nrm[lane] : T(-1);
+      int i = lane < R ? lane : 0x7fffffff;
+      wave_argmax(v, i);
+      if (lane == 0) {
+        sh_bq = i;
+        sh_best = v;
+      }
+    }
+    __syncthreads();
+  };
+  norms_and_candidate(0);
+
+  int64_t final_status = 0;
+  for (int t = 0; t < k; ++t) {
+    const int par = t & 1;
+    const unsigned tag = step_tag(a.epoch, t);
+    const int bq = sh_bq;
+    T best = sh_best;  // -1 when no column is left here
+    if (t == 0 && sh_bad) best = T(NAN);
+
+    // ---- publish the candidate's squared norm, then its rows t.. --------
+    if (tid < kValRep) put_value(&a.xval[tid * a.xrep + ((int64_t)par * G + g) * W], best, tag);
+    uint64_t* mycol = a.xrow + ((size_t)par * G + g) * a.lpad * W;
+    T myv = T(0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) myv = (q == bq) ? s[q] : myv;
+    if (j >= t && j < l) put_value(mycol + (size_t)j * W, myv, tag);
+
+    // ---- wave 0 gathers every workgroup's value and reduces (each lane
+    //      requests all of its words at once, G <= 256) --------------------
+    if (wid == 0) {
+      T cv = T(-2);
+      int ci = 0x7fffffff;
+      bool ok = true, nonfinite = false;
+      constexpr int PMAX = 4;
+      unsigned want = 0, got = 0, spins = 0;
+#pragma unroll
+      for (int c = 0; c < PMAX; ++c)
+        if (lane + 64 * c < G) want |= 1u << c;
+      const uint64_t* xw[PMAX];
+#pragma unroll
+      for (int c = 0; c < PMAX; ++c)
+        xw[c] = &a.xval[(g % kValRep) * a.xrep + ((int64_t)par * G + min(lane + 64 * c, G - 1)) * W];
+      T vals[PMAX];
+      while (got != want) {
+        uint64_t wv[W * PMAX];
+#pragma unroll
+        for (int c = 0; c < PMAX; ++c)
+#pragma unroll
+          for (int e = 0; e < W; ++e) wv[c * W + e] = wload(xw[c] + e);
+#pragma unroll
+        for (int c = 0; c < PMAX; ++c)
+          if (((want & ~got) >> c) & 1u) {
+            bool fresh = true;
+#pragma unroll
+            for (int e = 0; e < W; ++e) fresh &= (unsigned)(wv[c * W + e] >> 32) == tag;
+            if (fresh) {
+              vals[c] = word_value<T>(&wv[c * W]);
+              got |= 1u << c;
+            }
+          }
+        if (got != want && (++spins & 127u) == 0) {
+          if ((unsigned)wload(a.xflag) == a.epoch || spins > kSpinLimit / 2) {
+            wstore(a.xflag, (uint64_t)a.epoch);
+            ok = false;
+            break;
+          }
+        }
+      }
+      if (ok) {
+#pragma unroll
+        for (int c = 0; c < PMAX; ++c)
+          if ((want >> c) & 1u) {
+            const T v = vals[c];
+            const int i = lane + 64 * c;
+            if (!isfinite(v)) nonfinite = true;
+            if (v > cv || (v == cv && i < ci)) {
+              cv = v;
+              ci = i;
+            }
+          }
+      }
+      const bool any_fail = __any(!ok);
+      const bool any_nf = __any(nonfinite);
+      wave_argmax(cv, ci);
+      if (lane == 0) {
+        sh_gw = ci;
+        sh_code = 0;
+        if (any_fail) {
+          sh_code = 1;
+          sh_status = RPID_ERR_TIMEOUT;
+        } else if (any_nf) {
+          sh_code = 1;
+          sh_status = RPID_ERR_NONFINITE;
+        } else if (!(cv > T(0))) {  // every remaining column is zero in rows t..
+          sh_code = 1;
+          sh_status = t + 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (sh_code) {
+      final_status = sh_status;
+      break;
+    }
+    const int gw = sh_gw;
+    const bool winner = (g == gw);
+
+    // ---- the pivot column's rows t.., its norm, the reflector ------------
+    T w = T(0);
+    bool ok = true;
+    if (j >= t && j < l) {
+      if (winner)
+        w = myv;
+      else
+        ok = wait_value(a.xrow + (((size_t)par * G + gw) * a.lpad + j) * W, tag, w, a.xflag, a.epoch);
+    }
+    if (!ok) sh_abort = 1;
+    {
+      T w2 = w * w;
+#pragma unroll
+      for (int o = 32; o >= 1; o /= 2) w2 += __shfl_xor(w2, o, 64);
+      if (lane == 0) wpart[wid] = w2;
+      if (j == t) sh_w0 = w;
+    }
+    __syncthreads();
+    if (sh_abort) {
+      final_status = RPID_ERR_TIMEOUT;
+      break;
+    }
+    // every thread forms alpha and beta from the same values in the same order
+    T nw2 = wpart[0];
+    for (int i = 1; i < nwav; ++i) nw2 += wpart[i];
+    const T w0 = sh_w0;
+    const T nw = sqrt(nw2);
+    const T alpha = (w0 >= T(0)) ? -nw : nw;
+    const T beta = T(1) / (alpha * (alpha - w0));
+    const T vj = (j == t) ? w - alpha : ((j > t && j < l) ? w : T(0));
+
+    // ---- v^T x for every owned column, then x <- x - beta (v^T x) v -------
+    {
+      T vals[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) vals[q] = vj * s[q];
+      block_rowsum(vals, dsum);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) s[q] = fma(-beta * dsum[q], vj, s[q]);
+    // row t of R: the updated row t (alpha at the pivot, 0 for earlier
+    // pivots).  Thread t is the only reader of `alive` until the next
+    // reduction's barrier, so it also retires the pivot.
+    if (j == t) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int64_t col = row0 + q;
+        if (col < a.n) {
+          const bool is_piv = winner && q == bq;
+          a.Rf[t + col * a.ldr] = is_piv ? alpha : (alive[q] ? s[q] : T(0));
+        }
+      }
+      if (winner) alive[bq] = 0;
+    }
+    if (winner) {
+      if (tid == 0) {
+        a.J[t] = row0 + bq;
+        if (a.diag) a.diag[t] = fabs(alpha);
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) s[q] = (q == bq) ? T(0) : s[q];
+    }
+    if (t + 1 < k) norms_and_candidate(t + 1);
+  }
+  if (g == 0 && tid == 0) *a.status = final_status;
+}
+
+template <typename T, int R, int NTMAX>
+static int launch_cpqr(rpid_ctx ctx, CpqrArgs<T> a, int G, int nt) {
+  void* kargs[] = {&a};
+  const void* fn = reinterpret_cast<const void*>(cpqr_panel_kernel<T, R, NTMAX>);
+  int per_cu = 0;
+  RPID_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0));
+  if (per_cu < 1 || (int64_t)per_cu * ctx->num_cu < G) return RPID_ERR_LAUNCH;
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(nt), kargs, 0, ctx->stream);
+  if (e != hipSuccess) return RPID_ERR_LAUNCH;
+  return RPID_OK;
+}
+
+// R = 16 or 32 columns per workgroup and at most 512 threads keep the
+// column values, the reduction operands and the temporaries in registers.
+template <typename T, int NTMAX>
+static int cpqr_dispatch_R(rpid_ctx ctx, CpqrArgs<T> a, int R, int G, int nt) {
+  switch (R) {
+    case 16: return launch_cpqr<T, 16, NTMAX>(ctx, a, G, nt);
+    case 32: return launch_cpqr<T, 32, NTMAX>(ctx, a, G, nt);
+    default: return RPID_ERR_UNSUPPORTED;
+  }
+}
+
+template <typename T>
+int cpqr_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, int64_t l, int64_t k,
+               int64_t* J, T* Rf, int64_t ldr, T* diag, int64_t* status_dev) {
+  if (l < 1 || l > 512 || k < 1 || k > l || k > n) return RPID_ERR_UNSUPPORTED;
+  const int lpad = (int)((l + 63) / 64 * 64);
+  const int ntmax = lpad <= 256 ? 256 : 512;
+  int R = 32;
+  for (int c = 16; c <= 32; c *= 2)
+    if ((n + c - 1) / c <= ctx->num_cu) {
+      R = c;
+      break;
+    }
+  const int64_t G64 = (n + R - 1) / R;
+  if (G64 > ctx->num_cu || G64 > 256) return RPID_ERR_UNSUPPORTED;  // the poll covers 4 x 64 values
+  const int G = (int)G64;
+  constexpr int W = Words<T>::W;
+  Carve cv;
+  const int64_t xrep = ((int64_t)2 * G * W + 8191) / 8192 * 8192;
+  const size_t o_val = cv.take<uint64_t>((size_t)kValRep * xrep);
+  const size_t o_row = cv.take<uint64_t>((size_t)2 * G * lpad * W);
+  const size_t o_flag = cv.take<uint64_t>(1);
+  char* ucb = nullptr;
+  unsigned epoch = 0;
+  RPID_CHECK(exchange_buffer(ctx, cv.off, &ucb, &epoch));
+  CpqrArgs<T> a;
+  a.base = base;
+  a.rs = rs;
+  a.cs = cs;
+  a.n = n;
+  a.l = (int)l;
+  a.lpad = lpad;
+  a.k = (int)k;
+  a.J = J;
+  a.Rf = Rf;
+  a.ldr = ldr;
+  a.diag = diag;
+  a.xval = reinterpret_cast<uint64_t*>(ucb + o_val);
+  a.xrep = xrep;
+  a.xrow = reinterpret_cast<uint64_t*>(ucb + o_row);
+  a.xflag = reinterpret_cast<uint64_t*>(ucb + o_flag);
+  a.epoch = epoch;
+  a.status = status_dev;
+  if (ntmax == 256) return cpqr_dispatch_R<T, 256>(ctx, a, R, G, lpad);
+  return cpqr_dispatch_R<T, 512>(ctx, a, R, G, lpad);
+}
+
+template int cpqr_panel<double>(rpid_ctx, const double*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                int64_t*, double*, int64_t, double*, int64_t*);
+template int cpqr_panel<float>(rpid_ctx, const float*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                               int64_t*, float*, int64_t, float*, int64_t*);
 
 }  // namespace rpid

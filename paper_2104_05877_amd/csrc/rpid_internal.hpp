@@ -104,6 +104,13 @@ template <typename T>
 int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, int64_t k,
                int64_t* J, T* Lf, int64_t ldl, T* Uf, int64_t ldu, T* diag, size_t ws_off,
                int64_t* status_dev);
+// Column-pivoted Householder QR, k steps, of a sketch given as the panel
+// P(i, j) = base[i * rs + j * cs] = X(j, i) (n candidates, l rows of X):
+// pivots J, the k x n top of R in the original column order (Rf, ldr) and
+// |R(t, t)|, see lupp.hip.
+template <typename T>
+int cpqr_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, int64_t l, int64_t k,
+               int64_t* J, T* Rf, int64_t ldr, T* diag, int64_t* status_dev);
 // Workspace bytes lupp_panel needs for an n x k panel.
 size_t lupp_workspace_bytes(rpid_ctx ctx, int64_t n, int64_t k, int elem_bytes);
 

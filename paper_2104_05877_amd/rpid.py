@@ -48,6 +48,8 @@ _SIGS = {
     "rpid_sketch_power1": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
     "rpid_sketch_two_sided": (_i, [_P, _P, _i, _I, _I, _I, _P, _I, _P, _I, _I, _P, _I, _P, _I, _i]),
     "rpid_cur_sketch": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _P, _I]),
+    "rpid_select_columns_cpqr": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _P]),
+    "rpid_id_coeffs_cpqr": (_i, [_P, _i, _I, _I, _P, _P, _I, _P, _I]),
     "rpid_sketch_fp8": (_i, [_P, _P, _I, _I, _I, _P, _I, _I, _P, _I]),
     "rpid_select_columns": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, ctypes.POINTER(_I)]),
     "rpid_id_coeffs": (
@@ -248,6 +250,31 @@ def rpid_select_columns(ctx: Context, X: torch.Tensor, k: int, sync: bool = True
     )
     _check("rpid_select_columns", s, allow_positive=True)
     return J, Lf, Uf, diag, (keff.value if sync else None), (s if sync else None)
+
+
+def rpid_select_columns_cpqr(ctx: Context, X: torch.Tensor, k: int, sync: bool = True):
+    """Column-pivoted Householder QR of the sketch, k steps (Rand-CPQR).
+    Returns (J, Rf, diagR, k_eff, status); Rf is k x n in X's dtype."""
+    px, l, n, ldx = colmajor(X)
+    J = torch.empty(k, dtype=torch.int64, device=X.device)
+    Rf = empty_colmajor(k, n, X.dtype, X.device)
+    diag = torch.empty(k, dtype=X.dtype, device=X.device)
+    keff = _I(-1)
+    s = lib().rpid_select_columns_cpqr(ctx.handle, px, dtype_code(X), l, n, ldx, k, J.data_ptr(),
+                                       Rf.data_ptr(), Rf.stride(1), diag.data_ptr(),
+                                       ctypes.byref(keff) if sync else None)
+    _check("rpid_select_columns_cpqr", s, allow_positive=True)
+    return J, Rf, diag, (keff.value if sync else None), (s if sync else None)
+
+
+def rpid_id_coeffs_cpqr(ctx, k, J, Rf):
+    """Z = Rf(:, J)^{-1} Rf (k x n FP64)."""
+    pr, k2, n, ldr = colmajor(Rf)
+    Z = empty_colmajor(k, n, torch.float64, Rf.device)
+    s = lib().rpid_id_coeffs_cpqr(ctx.handle, dtype_code(Rf), k, n, J.data_ptr(), pr, ldr, Z.data_ptr(),
+                                  Z.stride(1))
+    _check("rpid_id_coeffs_cpqr", s)
+    return Z
 
 
 def rpid_id_coeffs(ctx, X, k, J, Lf, Uf, refine_steps=0, want_eta=False):

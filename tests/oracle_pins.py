@@ -459,3 +459,91 @@ def pin_two_sided_bounds(O, m=90, n=70, k=8, l=12, seeds=range(5)):
 
 ALL_PINS += [pin_two_sided_bruteforce, pin_row_id_structure, pin_two_sided_exact_rank,
              pin_cur_sketch_inverse, pin_two_sided_bounds]
+
+
+def pin_cpqr_lapack(O, seed=50, l=12, n=40, k=9):
+    """The CPQR pivots are LAPACK geqp3's (scipy, an independent
+    implementation with the same greedy rule) on a tie-free sketch, and the
+    top rows of R agree with its R (same reflector sign convention)."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((l, n)) * (1.0 + np.arange(n) % 7)[None, :]
+    f = O.cpqr_colwise(X, k, gaps=True)
+    assert f["gap"].min() > 1e-6
+    _, r, piv = sla.qr(X, pivoting=True, mode="economic")
+    assert np.array_equal(f["J"], piv[:k])
+    np.testing.assert_allclose(f["R"][:, piv], r[:k, :], rtol=0, atol=1e-12 * np.abs(X).max())
+
+
+def pin_cpqr_projection_greedy(O, seed=51, l=10, n=25, k=7):
+    """Pivot t maximises ||(I - Q Q^T) X(:, j)|| over the remaining columns,
+    Q an orthonormal basis of the columns already chosen (projections formed
+    explicitly, no reflectors), and |R(t, J[t])| is that largest norm."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((l, n))
+    f = O.cpqr_colwise(X, k)
+    chosen = []
+    for t in range(k):
+        if chosen:
+            q, _ = np.linalg.qr(X[:, chosen])
+            res = X - q @ (q.T @ X)
+        else:
+            res = X
+        nr = np.linalg.norm(res, axis=0)
+        nr[chosen] = -1.0
+        p = int(np.argmax(nr))
+        assert p == f["J"][t], (t, p, f["J"][t])
+        assert abs(f["diag"][t] - nr[p]) <= 1e-12 * nr[p]
+        chosen.append(p)
+
+
+def pin_cpqr_factor(O, seed=52, l=16, n=60, k=11):
+    """X(:, J)^T X = R_11^T R (the Gram identity of X(:, J) = Q R_11, X's top
+    part Q^T X = R), |R(t, J[t])| is non-increasing, R is zero at earlier
+    pivots, and Z = R_11^{-1} R equals the least-squares X(:, J)^+ X."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((l, n))
+    f = O.cpqr_colwise(X, k)
+    J, R = f["J"], f["R"]
+    np.testing.assert_allclose(X[:, J].T @ X, R[:, J].T @ R, rtol=0, atol=1e-11 * np.abs(X).max() ** 2 * l)
+    assert np.all(np.diff(f["diag"]) <= 1e-12 * f["diag"][0])
+    for t in range(k):
+        assert np.all(R[t, J[:t]] == 0.0)
+    Z = O.id_coeffs_cpqr(R, J)
+    Zls = np.linalg.lstsq(X[:, J], X, rcond=None)[0]
+    np.testing.assert_allclose(Z, Zls, rtol=0, atol=1e-9 * np.abs(Zls).max())
+
+
+def pin_cpqr_exact_rank_and_zero(O, seed=53, m=70, n=50, k=6, l=9):
+    """rank(A) = k: the ID from the CPQR pivots of its sketch reproduces A;
+    a sketch whose columns beyond two are exactly zero stops at step 3."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+    X = O.sketch(a, rng.standard_normal((l, m)))
+    f = O.cpqr_colwise(X, k)
+    Z = O.id_coeffs_cpqr(f["R"], f["J"])
+    assert np.linalg.norm(a - a[:, f["J"]] @ Z) <= 1e-9 * np.linalg.norm(a)
+    X0 = np.zeros((l, n))
+    X0[:, 4] = rng.standard_normal(l)
+    X0[:, 17] = rng.standard_normal(l)
+    f0 = O.cpqr_colwise(X0, 5)
+    assert f0["status"] == 3 and f0["k_eff"] == 2 and set(f0["J"]) == {4, 17}
+
+
+ALL_PINS += [pin_cpqr_lapack, pin_cpqr_projection_greedy, pin_cpqr_factor, pin_cpqr_exact_rank_and_zero]
+
+
+def pin_cpqr_ties(O, seed=54, l=6, n=14):
+    """Equal norms go to the smaller column: columns 3 and 8 are x and -x,
+    the largest (exactly equal norms), so the first pivot is 3; after it
+    column 8 has nothing left and column 5, scaled to twice any other
+    column's norm, is next."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((l, n))
+    X[:, 3] = 10.0 * rng.standard_normal(l)
+    X[:, 8] = -X[:, 3]
+    X[:, 5] *= 2.0 * np.linalg.norm(np.delete(X, [3, 5, 8], axis=1), axis=0).max() / np.linalg.norm(X[:, 5])
+    f = O.cpqr_colwise(X, 3)
+    assert f["J"][0] == 3 and f["J"][1] != 8
+
+
+ALL_PINS += [pin_cpqr_ties]

@@ -1,0 +1,148 @@
+"""GPU tests of Rand-CPQR's pivoting (column-pivoted Householder QR of the
+sketch, eq. def_QRCP) against the FP64 oracle: pivots, the R factor, the ID
+coefficients Z = R_11^{-1} R and the ID residual built on them."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle.rpid_oracle as O  # noqa: E402
+from paper_2104_05877_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[cpqr]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2104_05877_amd import rpid
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return rpid
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context(0)
+    yield c
+    c.close()
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def dev(a, dt=torch.float64):
+    return inputs.torch_colmajor(a, dt, "cuda")
+
+
+def first_close(gap, thr):
+    close = gap < thr
+    return int(np.argmax(close)) if close.any() else len(gap)
+
+
+# (l, n, k, seed): one workgroup column block of 16 or 32 columns, 256 or 512
+# threads, ragged n, k up to l = 512
+SHAPES = [(16, 100, 10, 1), (64, 1000, 64, 2), (300, 5000, 200, 3), (512, 2048, 512, 4), (272, 8192, 256, 5)]
+
+
+@pytest.mark.parametrize("l,n,k,seed", SHAPES)
+def test_cpqr_fp64_against_oracle(R, ctx, l, n, k, seed):
+    """FP64: the pivots equal the oracle's up to the first step whose two
+    largest norms are within 1e-9 relative; the rows of R up to there agree
+    to 1e-12 l max|X|."""
+    say("fp64", l, n, k)
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((l, n)) * 10.0 ** rng.uniform(-1, 1, n)[None, :]
+    J, Rf, diag, keff, st = R.rpid_select_columns_cpqr(ctx, dev(X), k)
+    assert st == 0 and keff == k
+    f = O.cpqr_colwise(X, k, gaps=True)
+    fc = first_close(f["gap"], 1e-9)
+    Jg = J.cpu().numpy()
+    say("matched prefix", fc, "of", k)
+    assert np.array_equal(Jg[:fc], f["J"][:fc])
+    if fc == k:
+        assert np.array_equal(Jg, f["J"])
+    tol = 1e-12 * l * np.abs(X).max()
+    err = np.abs(host(Rf)[:fc] - f["R"][:fc]).max()
+    say("max |dR|", err, "tol", tol)
+    assert err <= tol
+    np.testing.assert_allclose(host(diag)[:fc], f["diag"][:fc], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("l,n,k,seed", [(64, 1000, 64, 6), (272, 8192, 256, 7)])
+def test_cpqr_fp32_against_oracle(R, ctx, l, n, k, seed):
+    """FP32 sketch (columns scaled over two decades, so that norms are spread):
+    pivots equal the oracle's (FP64 on the same FP32 values) up to the first
+    step whose two largest norms are within 1e-4 relative (FP32 norms carry
+    relative errors of order 1e-6 after many reflectors)."""
+    say("fp32", l, n, k)
+    rng = np.random.default_rng(seed)
+    Xd = dev(rng.standard_normal((l, n)) * 10.0 ** rng.uniform(-1, 1, n)[None, :], torch.float32)
+    X = host(Xd)
+    J, Rf, diag, keff, st = R.rpid_select_columns_cpqr(ctx, Xd, k)
+    assert st == 0
+    f = O.cpqr_colwise(X, k, gaps=True)
+    fc = first_close(f["gap"], 1e-4)
+    say("matched prefix", fc, "of", k, "; GPU pivots equal to the oracle's:",
+        int(np.sum(J.cpu().numpy() == f["J"])))
+    assert np.array_equal(J.cpu().numpy()[:fc], f["J"][:fc])
+
+
+@pytest.mark.parametrize("dt", ["float64", "float32"])
+def test_cpqr_id_against_oracle(R, ctx, dt):
+    """Rand-CPQR end to end on a sketch of a spectral matrix: Z from the GPU
+    QR, and the ID residual within 1e-9 (FP64) or 1.05x (FP32) of the oracle's;
+    the Rand-LUPP residual on the same sketch is printed beside it."""
+    m, n, k, l = 1200, 1000, 40, 48
+    A, Om = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 21)
+    tdt = getattr(torch, dt)
+    Ad = dev(A, tdt)
+    X = R.rpid_sketch(ctx, Ad, dev(Om, tdt))
+    J, Rf, _, _, st = R.rpid_select_columns_cpqr(ctx, X, k)
+    assert st == 0
+    Z = R.rpid_id_coeffs_cpqr(ctx, k, J, Rf)
+    r_gpu = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, J, Z=Z)
+    Xh = host(X)
+    f = O.cpqr_colwise(Xh, k)
+    Zo = O.id_coeffs_cpqr(f["R"], f["J"])
+    a_s = host(Ad)
+    r_or = O.residuals(a_s, f["J"], Z=Zo, only=("id",))["id"]
+    Jl = O.lupp_colwise(Xh, k)["J"]
+    r_lupp = O.residuals(a_s, Jl, Z=O.id_coeffs(Xh, Jl, k), only=("id",))["id"]
+    say(dt, "cpqr id residual gpu", r_gpu, "oracle", r_or, "lupp (oracle)", r_lupp)
+    if dt == "float64":
+        assert np.array_equal(J.cpu().numpy(), f["J"])
+        np.testing.assert_allclose(host(Z), Zo, rtol=0, atol=1e-9 * np.abs(Zo).max())
+        assert abs(r_gpu - r_or) <= 1e-9 * r_or
+    else:
+        assert r_gpu <= 1.05 * r_or
+
+
+def test_cpqr_zero_columns_stop(R, ctx):
+    """Only columns 4 and 17 are nonzero: two steps, then every remaining
+    column is exactly zero, so the status is 3 and k_eff 2."""
+    rng = np.random.default_rng(8)
+    X = np.zeros((9, 50))
+    X[:, 4] = rng.standard_normal(9)
+    X[:, 17] = rng.standard_normal(9)
+    J, Rf, diag, keff, st = R.rpid_select_columns_cpqr(ctx, dev(X), 5)
+    assert st == 3 and keff == 2
+    assert set(J.cpu().numpy()[:2].tolist()) == {4, 17}
+
+
+def test_cpqr_errors(R, ctx):
+    X = np.ones((8, 40))
+    X[3, 11] = np.nan
+    with pytest.raises(R.RpidError) as e:
+        R.rpid_select_columns_cpqr(ctx, dev(X), 4)
+    assert e.value.status == -100
+    with pytest.raises(R.RpidError) as e:
+        R.rpid_select_columns_cpqr(ctx, dev(np.ones((600, 700))), 4)
+    assert e.value.status == -4

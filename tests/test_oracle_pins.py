@@ -67,6 +67,15 @@ MUTANTS = {
     "cheap CUR core not inverted": ("return np.linalg.solve(S, np.eye(S.shape[0]))", "return S"),
     "cheap CUR core from S transposed": ("return np.linalg.solve(S, np.eye(S.shape[0]))",
                                          "return np.linalg.solve(S.T, np.eye(S.shape[0]))"),
+    "CPQR norms over all rows": ("norms = np.sqrt(np.sum(S[t:, :] ** 2, axis=0))",
+                                 "norms = np.sqrt(np.sum(S ** 2, axis=0))"),
+    "CPQR ties to the largest column": ("p = int(cand.argmax())  # the first maximum",
+                                        "p = int(len(cand) - 1 - cand[::-1].argmax())"),
+    "CPQR reflector sign flipped": ("alpha = -np.linalg.norm(w) if w[0] >= 0.0 else np.linalg.norm(w)",
+                                    "alpha = np.linalg.norm(w) if w[0] >= 0.0 else -np.linalg.norm(w)"),
+    "CPQR update without beta": ("S[t:, cols] -= beta * np.outer(v, d)", "S[t:, cols] -= np.outer(v, d)"),
+    "CPQR Z from the transposed R_11": ("Z = sla.solve_triangular(R[:k, J], R[:k, :], lower=False)",
+                                        "Z = sla.solve_triangular(R[:k, J].T, R[:k, :], lower=True)"),
     "row ID residual with C instead of R": ('out["rowid"] = nrm(A - _f64(W) @ R) / na',
                                             'out["rowid"] = nrm(A - _f64(W) @ R[:, ::-1]) / na'),
 }
