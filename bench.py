@@ -271,6 +271,50 @@ def cpqr_report(torch, R, ctx, A, Om, plain):
     return out
 
 
+def sparse_report(torch, R, ctx, A, Om):
+    """Sparse and structured sketches (Sec. 2.2): the sparse sign embedding
+    (zeta = 8, scale 1/sqrt(8)) on the main dense input, and the CSC sketch of
+    an SNN matrix (eq. snn-def) 65536 x 65536, r = 400, s_i = 2/i (i <= 100)
+    then 1/i, x_i and y_i with 0.1 % nonzeros (FP32 values, l = 272, Gaussian
+    and sparse sign embeddings), followed by Rand-LUPP's column selection."""
+    import numpy as np
+
+    from paper_2104_05877_amd import inputs
+
+    def timed(fn, reps=5):
+        out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    rng = np.random.default_rng(99)
+    m = A.shape[0]
+    rows, signs = inputs.sparse_sign_draws(rng, m, L, 8)
+    rows_d, signs_d = torch.from_numpy(rows).cuda(), torch.from_numpy(signs).cuda()
+    _, ms_ss_dense = timed(lambda: R.rpid_sketch_sparse_sign(ctx, A, rows_d, signs_d, L, 8 ** -0.5))
+    _, ms_gauss_dense = timed(lambda: R.rpid_sketch(ctx, A, Om))
+    ms_ = 65536
+    i = np.arange(1, 401, dtype=np.float64)
+    sv = np.where(i <= 100, 2.0 / i, 1.0 / i)
+    cp, ri, va = inputs.snn_csc(np.random.default_rng(98), ms_, ms_, sv, 0.001)
+    Ac = R.CSC(torch.from_numpy(cp).cuda(), torch.from_numpy(ri).cuda(), torch.from_numpy(va).float().cuda(), ms_, ms_)
+    G = inputs.torch_gaussian(L, ms_, 97, "cuda", dtype=torch.float32).T.contiguous().T
+    X, ms_csc = timed(lambda: R.rpid_sketch_csc(ctx, Ac, G))
+    r2, s2 = inputs.sparse_sign_draws(rng, ms_, L, 8)
+    _, ms_csc_ss = timed(lambda: R.rpid_sketch_csc_sparse_sign(ctx, Ac, torch.from_numpy(r2).cuda(),
+                                                               torch.from_numpy(s2).cuda(), L, 8 ** -0.5))
+    (J, _, _, _, _, _), ms_sel = timed(lambda: R.rpid_select_columns(ctx, X, K, sync=False), reps=3)
+    return {"sparse_sign_dense_ms": ms_ss_dense, "gaussian_dense_ms": ms_gauss_dense,
+            "snn65536_nnz": int(len(va)), "csc_gaussian_sketch_ms": ms_csc, "csc_sparse_sign_sketch_ms": ms_csc_ss,
+            "csc_select_columns_ms": ms_sel,
+            "csc_gaussian_gflops": 2.0 * len(va) * L / (ms_csc * 1e-3) / 1e9}
+
+
 def calibration_copy(torch):
     """One elementwise kernel that reads CALIB_MIB MiB and writes CALIB_MIB MiB
     (a negating copy: a plain same-dtype copy would go to the DMA engines),
@@ -445,8 +489,9 @@ def main():
         A, Om = data[args.mode]
         rep = two_sided_report(torch, R, ctx, A, Om, None)
         rep_qr = cpqr_report(torch, R, ctx, A, Om, None)
+        rep_sp = sparse_report(torch, R, ctx, A, Om)
         ctx.close()
-        print(json.dumps({"mode": args.mode, "two_sided": rep, "cpqr": rep_qr}), flush=True)
+        print(json.dumps({"mode": args.mode, "two_sided": rep, "cpqr": rep_qr, "sparse": rep_sp}), flush=True)
         return
     results = {}
     order = [args.mode] + [m for m in ("bf16", "f32", "f64") if m != args.mode]
@@ -530,6 +575,8 @@ def main():
         line["two_sided"] = two_sided_report(torch, R, ctx, *data[args.mode], main_r)
         log("Rand-CPQR report")
         line["cpqr"] = cpqr_report(torch, R, ctx, *data[args.mode], main_r)
+        log("sparse-sketch report")
+        line["sparse"] = sparse_report(torch, R, ctx, *data[args.mode])
     if not args.no_learned and not args.only_main:
         log("learned-rank report")
         line["learned_rank"] = learned_report(torch, ctx)

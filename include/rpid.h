@@ -186,6 +186,57 @@ int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, 
                         int64_t ldu, void* diagU, int64_t* k_eff);
 
 /*
+ * Sparse sign embedding (Sec. 2.2, third embedding): Gamma (l x m) has in
+ * column i the entries signs[i, s] (+-1) at rows rows[i, s], s < zeta, times
+ * `scale`; X = Gamma A for a dense A.  The draws are the caller's:
+ *   rows   int32 m x zeta, row-major (rows[i * zeta + s]), values in [0, l),
+ *          distinct within a row (an index outside [0, l) adds nothing)
+ *   signs  int8 m x zeta, row-major, +1 or -1
+ *   zeta   1 <= zeta <= min(l, 64); scale > 0 (the paper's 2 <= zeta <= l;
+ *          its normalisation is left to the caller: pivots do not depend on it)
+ *   A, a_t, m, n, lda, X, x_t, ldx, l as for rpid_sketch, (a_t, x_t) in
+ *          {(F64,F64), (F32,F32), (BF16,F32)}
+ * The embedding is expanded to exact +-1 entries in A's type and applied by
+ * the dense MFMA sketch; the scale multiplies X afterwards.
+ */
+int rpid_sketch_sparse_sign(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                            int64_t lda, const int32_t* rows, const int8_t* signs, int64_t zeta,
+                            int64_t l, double scale, void* X, rpid_dtype x_t, int64_t ldx);
+
+/*
+ * Sketch of a sparse A given in compressed sparse column form (the sparse
+ * inputs of Sec. 5, e.g. eq. snn-def): X = Gamma A.
+ *   colptr  int64[n + 1], rowidx int64[nnz], vals[nnz] of type v_t (F64 or
+ *           F32), device; column j holds entries colptr[j] .. colptr[j+1]-1
+ *           (pointers are clamped to [0, nnz]; row indices outside [0, m)
+ *           are skipped)
+ *   Gamma   l x m, ldg >= l, type v_t (dense embedding, e.g. Gaussian)
+ *   X       l x n, ldx >= l, type v_t (output); 1 <= l <= 1024
+ * Deterministic: each column's nonzeros are added in storage order.
+ */
+int rpid_sketch_csc(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, const void* vals,
+                    rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz, const void* Gamma, int64_t ldg,
+                    int64_t l, void* X, int64_t ldx);
+
+/*
+ * The same CSC sketch with a sparse sign embedding (rows, signs, zeta, scale
+ * as for rpid_sketch_sparse_sign); X is l x n of type v_t.
+ */
+int rpid_sketch_csc_sparse_sign(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx,
+                                const void* vals, rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz,
+                                const int32_t* rows, const int8_t* signs, int64_t zeta, int64_t l,
+                                double scale, void* X, int64_t ldx);
+
+/*
+ * Dense columns of a CSC matrix: C(:, t) = A(:, J[t]) (m x k, ldc >= m, type
+ * v_t), e.g. the skeleton C of a sparse A; J = NULL with k = n densifies all
+ * of A.  Columns J[t] outside [0, n) come out as zeros.
+ */
+int rpid_csc_gather(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, const void* vals,
+                    rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz, int64_t k, const int64_t* J,
+                    void* C, int64_t ldc);
+
+/*
  * Rand-CPQR skeleton selection on the same sketch (the comparison pivoting
  * of Sec. 5; column-pivoted QR of eq. def_QRCP): k steps of Householder QR
  * with column pivoting on X.  Step t picks the remaining column with the

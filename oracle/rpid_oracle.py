@@ -34,6 +34,10 @@ randomized pivoting algorithms for CUR and interpolative decompositions":
 * cpqr_colwise      -- column-pivoted Householder QR of the sketch, eq.
                        (def_QRCP): the pivoting of Rand-CPQR (Sec. 5).
 * id_coeffs_cpqr    -- Z = R_11^{-1} R_top from that QR (Z = X_1^+ X).
+* sparse_sign_matrix, sketch_sparse_sign -- the sparse sign embedding of
+                       Sec. 2.2 (zeta signed entries per column) and its sketch.
+* csc_dense, sketch_csc -- a matrix in compressed sparse column form (the
+                       sparse inputs, eq. snn-def) and its sketch.
 
 Everything is float64 numpy.  Library primitives used as single steps: matmul,
 QR, triangular/linear solves, SVD (for spectral norms only).
@@ -73,6 +77,10 @@ __all__ = [
     "decompose_two_sided",
     "cpqr_colwise",
     "id_coeffs_cpqr",
+    "sparse_sign_matrix",
+    "sketch_sparse_sign",
+    "csc_dense",
+    "sketch_csc",
     "NonFiniteInput",
 ]
 
@@ -501,3 +509,39 @@ def id_coeffs_cpqr(R, J):
     Z = sla.solve_triangular(R[:k, J], R[:k, :], lower=False)
     Z[:, J] = np.eye(k)
     return Z
+
+
+# --------------------------------------------------------------------------
+# Sec. 2.2: sparse sign embeddings; sparse A in compressed sparse column form
+# --------------------------------------------------------------------------
+def sparse_sign_matrix(rows, signs, l):
+    """The l x m sparse sign embedding (unscaled): column i holds signs[i, s]
+    at row rows[i, s] for s < zeta and zeros elsewhere."""
+    rows = np.asarray(rows)
+    signs = np.asarray(signs)
+    m, zeta = rows.shape
+    G = np.zeros((l, m))
+    for i in range(m):
+        for s_ in range(zeta):
+            G[rows[i, s_], i] = float(signs[i, s_])
+    return G
+
+
+def sketch_sparse_sign(A, rows, signs, l, scale):
+    """X = scale * S A with S = sparse_sign_matrix(rows, signs, l)."""
+    return float(scale) * (sparse_sign_matrix(rows, signs, l) @ _f64(A))
+
+
+def csc_dense(colptr, rowidx, vals, m, n):
+    """The dense m x n matrix whose column j holds vals[p] at row rowidx[p]
+    for colptr[j] <= p < colptr[j + 1]."""
+    A = np.zeros((m, n))
+    for j in range(n):
+        for p in range(int(colptr[j]), int(colptr[j + 1])):
+            A[int(rowidx[p]), j] = float(vals[p])
+    return A
+
+
+def sketch_csc(colptr, rowidx, vals, m, n, Gamma):
+    """X = Gamma A for A given in compressed sparse column form."""
+    return _f64(Gamma) @ csc_dense(colptr, rowidx, vals, m, n)

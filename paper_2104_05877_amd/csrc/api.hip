@@ -1,6 +1,7 @@
 // C-ABI entry points of librpid (declared in include/rpid.h): argument
 // validation, workspace sizing and the order of the kernels of each step.
 #include <algorithm>
+#include <cmath>
 #include <new>
 
 #include "rpid_internal.hpp"
@@ -809,6 +810,122 @@ int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, 
   if (st < 0) return (int)st;
   *k_eff = (st == 0) ? k : st - 1;
   return (int)st;
+}
+
+// ---------------------------------------------------------------------------
+int rpid_sketch_sparse_sign(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                            int64_t lda, const int32_t* rows, const int8_t* signs, int64_t zeta,
+                            int64_t l, double scale, void* X, rpid_dtype x_t, int64_t ldx) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (!rows) return -7;
+  if (!signs) return -8;
+  if (zeta < 1 || zeta > 64 || zeta > l) return -9;
+  if (l < 1 || l > 1024) return -10;
+  if (!(scale > 0.0) || !std::isfinite(scale)) return -11;
+  if (!X) return -12;
+  if (ldx < l) return -14;
+  const bool f64 = a_t == RPID_F64 && x_t == RPID_F64;
+  const bool f32 = a_t == RPID_F32 && x_t == RPID_F32;
+  const bool bf = a_t == RPID_BF16 && x_t == RPID_F32;
+  if (!(f64 || f32 || bf)) return RPID_ERR_UNSUPPORTED;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_pt = cv.take<char>((size_t)m * l * esize(a_t));
+  const size_t ws_sk = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, ws_sk + sketch_workspace_bytes(ctx, m, n, l, f64 ? 8 : 4)));
+  // the embedding's transpose (m x l, exact +-1 entries) feeds the dense sketch
+  if (f64) {
+    double* pt = ws_ptr<double>(ctx, o_pt);
+    RPID_CHECK(expand_sparse_sign<double>(ctx, m, l, (int)zeta, rows, signs, pt, m, 1, true));
+    RPID_CHECK(sketch_f64(ctx, pt, m, (const double*)A, lda, m, n, l, (double*)X, ldx, ws_sk));
+    return scale_matrix<double>(ctx, l, n, (double*)X, ldx, scale);
+  }
+  if (f32) {
+    float* pt = ws_ptr<float>(ctx, o_pt);
+    RPID_CHECK(expand_sparse_sign<float>(ctx, m, l, (int)zeta, rows, signs, pt, m, 1, true));
+    RPID_CHECK(sketch_f32(ctx, pt, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk));
+    return scale_matrix<float>(ctx, l, n, (float*)X, ldx, (float)scale);
+  }
+  uint16_t* pt = ws_ptr<uint16_t>(ctx, o_pt);
+  RPID_CHECK(expand_sparse_sign<uint16_t>(ctx, m, l, (int)zeta, rows, signs, pt, m, 1, true));
+  RPID_CHECK(sketch_bf16(ctx, pt, m, (const uint16_t*)A, lda, m, n, l, (float*)X, ldx, ws_sk));
+  return scale_matrix<float>(ctx, l, n, (float*)X, ldx, (float)scale);
+}
+
+static int csc_args(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, const void* vals,
+                    rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz) {
+  if (!ctx) return -1;
+  if (!colptr) return -2;
+  if (!rowidx && nnz > 0) return -3;
+  if (!vals && nnz > 0) return -4;
+  if (!(v_t == RPID_F64 || v_t == RPID_F32)) return -5;
+  if (m < 1) return -6;
+  if (n < 1) return -7;
+  if (nnz < 0) return -8;
+  return RPID_OK;
+}
+
+int rpid_sketch_csc(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, const void* vals,
+                    rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz, const void* Gamma, int64_t ldg,
+                    int64_t l, void* X, int64_t ldx) {
+  RPID_CHECK(csc_args(ctx, colptr, rowidx, vals, v_t, m, n, nnz));
+  if (!Gamma) return -9;
+  if (ldg < l) return -10;
+  if (l < 1 || l > 1024) return -11;
+  if (!X) return -12;
+  if (ldx < l) return -13;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  if (v_t == RPID_F64)
+    return csc_sketch<double>(ctx, m, n, nnz, colptr, rowidx, (const double*)vals, (const double*)Gamma,
+                              ldg, l, (double*)X, ldx);
+  return csc_sketch<float>(ctx, m, n, nnz, colptr, rowidx, (const float*)vals, (const float*)Gamma, ldg, l,
+                           (float*)X, ldx);
+}
+
+int rpid_sketch_csc_sparse_sign(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx,
+                                const void* vals, rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz,
+                                const int32_t* rows, const int8_t* signs, int64_t zeta, int64_t l,
+                                double scale, void* X, int64_t ldx) {
+  RPID_CHECK(csc_args(ctx, colptr, rowidx, vals, v_t, m, n, nnz));
+  if (!rows) return -9;
+  if (!signs) return -10;
+  if (zeta < 1 || zeta > 64 || zeta > l) return -11;
+  if (l < 1 || l > 1024) return -12;
+  if (!(scale > 0.0) || !std::isfinite(scale)) return -13;
+  if (!X) return -14;
+  if (ldx < l) return -15;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_g = cv.take<char>((size_t)l * m * esize(v_t));
+  RPID_CHECK(ensure_workspace(ctx, cv.off));
+  // the embedding itself (l x m, columns contiguous) for the column-wise CSC sketch
+  if (v_t == RPID_F64) {
+    double* g = ws_ptr<double>(ctx, o_g);
+    RPID_CHECK(expand_sparse_sign<double>(ctx, m, l, (int)zeta, rows, signs, g, 1, l, false));
+    RPID_CHECK(csc_sketch<double>(ctx, m, n, nnz, colptr, rowidx, (const double*)vals, g, l, l, (double*)X, ldx));
+    return scale_matrix<double>(ctx, l, n, (double*)X, ldx, scale);
+  }
+  float* g = ws_ptr<float>(ctx, o_g);
+  RPID_CHECK(expand_sparse_sign<float>(ctx, m, l, (int)zeta, rows, signs, g, 1, l, false));
+  RPID_CHECK(csc_sketch<float>(ctx, m, n, nnz, colptr, rowidx, (const float*)vals, g, l, l, (float*)X, ldx));
+  return scale_matrix<float>(ctx, l, n, (float*)X, ldx, (float)scale);
+}
+
+int rpid_csc_gather(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, const void* vals,
+                    rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz, int64_t k, const int64_t* J,
+                    void* C, int64_t ldc) {
+  RPID_CHECK(csc_args(ctx, colptr, rowidx, vals, v_t, m, n, nnz));
+  if (k < 1 || (!J && k != n)) return -9;
+  if (!C) return -11;
+  if (ldc < m) return -12;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  if (v_t == RPID_F64)
+    return csc_gather<double>(ctx, m, n, nnz, colptr, rowidx, (const double*)vals, k, J, (double*)C, ldc);
+  return csc_gather<float>(ctx, m, n, nnz, colptr, rowidx, (const float*)vals, k, J, (float*)C, ldc);
 }
 
 // ---------------------------------------------------------------------------

@@ -130,6 +130,24 @@ int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A
 int sketch_at_bf16(rpid_ctx ctx, const uint16_t* Ot, int64_t ldot, const uint16_t* A, int64_t lda,
                    int64_t m, int64_t n, int64_t l, float* Yt, int64_t ldyt, size_t ws_off);
 size_t sketch_workspace_bytes(rpid_ctx ctx, int64_t m, int64_t n, int64_t l, int elem_acc);
+
+// Sparse and structured sketches (sparse.hip).  expand_sparse_sign writes
+// the l x m sparse sign embedding (+-1 entries, unscaled) as
+// out[r * rs + i * cs]; i_fast picks the faster-varying index of the write.
+template <typename TE>
+int expand_sparse_sign(rpid_ctx ctx, int64_t m, int64_t l, int zeta, const int32_t* rows,
+                       const int8_t* signs, TE* out, int64_t rs, int64_t cs, bool i_fast);
+template <typename T>
+int scale_matrix(rpid_ctx ctx, int64_t rows, int64_t cols, T* X, int64_t ldx, T scale);
+// X = Gamma A for a CSC matrix A (m x n, nnz stored entries); Gamma l x m.
+template <typename T>
+int csc_sketch(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+               const int64_t* rowidx, const T* vals, const T* Gamma, int64_t ldg, int64_t l, T* X,
+               int64_t ldx);
+// C(:, t) = A(:, J[t]) for a CSC matrix (J null: all n columns, k = n).
+template <typename T>
+int csc_gather(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+               const int64_t* rowidx, const T* vals, int64_t k, const int64_t* J, T* C, int64_t ldc);
 bool residual_stream_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const uint16_t* R,
                           int64_t ldr, const uint16_t* Pt, int64_t ldpt, const uint16_t* Q,
                           int64_t ldq, double* partials, int64_t* count, int* err);

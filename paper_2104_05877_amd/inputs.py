@@ -16,6 +16,14 @@ matrices stand in for them, with spectra controlled exactly):
 * ``nonneg_lowrank``: A = |F| |G| + uniform noise (non-negative entries).
 * ``gaussian_embedding``: Omega with iid N(0, 1) entries (the embedding of
   Section 2.2 with mean 0; the scale does not change the pivots).
+* ``sparse_sign_draws``: the random draws of a sparse sign embedding (Section
+  2.2): for each of its m columns, zeta distinct row coordinates uniform over
+  the l rows and zeta independent signs.
+* ``snn_csc``: a sparse non-negative (SNN) matrix sum_i s_i x_i y_i^T with
+  sparse non-negative x_i, y_i (eq. snn-def), in compressed sparse column
+  form.  The paper leaves the sparsity of x_i, y_i open: here each x_i
+  (y_i) has round(rho m) (round(rho n)) nonzeros at uniform positions with
+  values uniform on (0, 1).
 """
 from __future__ import annotations
 
@@ -222,3 +230,44 @@ def torch_stream_case(index, lmax, device, seed=0, **ranges):
     a16 = a64.T.contiguous().bfloat16().T
     om16 = om64.T.contiguous().bfloat16().T
     return a64, om64, a16, om16, fam
+
+
+def sparse_sign_draws(rng: np.random.Generator, m: int, l: int, zeta: int):
+    """rows (m x zeta int32) and signs (m x zeta int8): column i of the
+    embedding has the value signs[i, s] at row rows[i, s], s < zeta; the rows
+    of a column are distinct and uniform (the first zeta of a random
+    permutation of the l rows), the signs independent Rademacher."""
+    keys = rng.random((m, l))
+    rows = np.argpartition(keys, zeta - 1, axis=1)[:, :zeta].astype(np.int32)
+    signs = np.where(rng.random((m, zeta)) < 0.5, -1, 1).astype(np.int8)
+    return np.ascontiguousarray(rows), np.ascontiguousarray(signs)
+
+
+def snn_csc(rng: np.random.Generator, m: int, n: int, s: np.ndarray, rho: float):
+    """SNN matrix sum_i s_i x_i y_i^T (eq. snn-def) as (colptr int64[n+1],
+    rowidx int64[nnz], vals float64[nnz]) with sorted row indices per
+    column; x_i, y_i have round(rho m), round(rho n) nonzeros (at least 1)
+    at uniform positions, values uniform on (0, 1)."""
+    r = len(s)
+    px = max(1, int(round(rho * m)))
+    py = max(1, int(round(rho * n)))
+    cols = {}
+    for i in range(r):
+        xi = rng.choice(m, px, replace=False)
+        xv = rng.random(px)
+        yi = rng.choice(n, py, replace=False)
+        yv = rng.random(py)
+        for jj, yy in zip(yi, yv):
+            d = cols.setdefault(int(jj), {})
+            w = s[i] * yy
+            for ii, xx in zip(xi, xv):
+                d[int(ii)] = d.get(int(ii), 0.0) + w * xx
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    rowidx, vals = [], []
+    for j in range(n):
+        d = cols.get(j, {})
+        keys = sorted(d)
+        rowidx.extend(keys)
+        vals.extend(d[k] for k in keys)
+        colptr[j + 1] = colptr[j] + len(keys)
+    return colptr, np.array(rowidx, dtype=np.int64), np.array(vals, dtype=np.float64)

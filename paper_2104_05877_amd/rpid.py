@@ -49,6 +49,11 @@ _SIGS = {
     "rpid_sketch_two_sided": (_i, [_P, _P, _i, _I, _I, _I, _P, _I, _P, _I, _I, _P, _I, _P, _I, _i]),
     "rpid_cur_sketch": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _P, _I]),
     "rpid_select_columns_cpqr": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _P]),
+    "rpid_sketch_sparse_sign": (_i, [_P, _P, _i, _I, _I, _I, _P, _P, _I, _I, ctypes.c_double, _P, _i, _I]),
+    "rpid_sketch_csc": (_i, [_P, _P, _P, _P, _i, _I, _I, _I, _P, _I, _I, _P, _I]),
+    "rpid_sketch_csc_sparse_sign": (_i, [_P, _P, _P, _P, _i, _I, _I, _I, _P, _P, _I, _I, ctypes.c_double,
+                                         _P, _I]),
+    "rpid_csc_gather": (_i, [_P, _P, _P, _P, _i, _I, _I, _I, _I, _P, _P, _I]),
     "rpid_id_coeffs_cpqr": (_i, [_P, _i, _I, _I, _P, _P, _I, _P, _I]),
     "rpid_sketch_fp8": (_i, [_P, _P, _I, _I, _I, _P, _I, _I, _P, _I]),
     "rpid_select_columns": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, ctypes.POINTER(_I)]),
@@ -250,6 +255,74 @@ def rpid_select_columns(ctx: Context, X: torch.Tensor, k: int, sync: bool = True
     )
     _check("rpid_select_columns", s, allow_positive=True)
     return J, Lf, Uf, diag, (keff.value if sync else None), (s if sync else None)
+
+
+def rpid_sketch_sparse_sign(ctx: Context, A: torch.Tensor, rows: torch.Tensor, signs: torch.Tensor, l: int,
+                            scale: float) -> torch.Tensor:
+    """X = scale * S A with S the l x m sparse sign embedding given by rows
+    (m x zeta int32) and signs (m x zeta int8), both contiguous on the device."""
+    pa, m, n, lda = colmajor(A)
+    if rows.dtype != torch.int32 or signs.dtype != torch.int8 or rows.shape != signs.shape or rows.shape[0] != m:
+        raise ValueError("rows (int32) and signs (int8) must be m x zeta")
+    rows, signs = rows.contiguous(), signs.contiguous()
+    out_dtype = torch.float32 if A.dtype == torch.bfloat16 else A.dtype
+    X = empty_colmajor(l, n, out_dtype, A.device)
+    px, _, _, ldx = colmajor(X)
+    s = lib().rpid_sketch_sparse_sign(ctx.handle, pa, dtype_code(A), m, n, lda, rows.data_ptr(), signs.data_ptr(),
+                                      rows.shape[1], l, float(scale), px, dtype_code(X), ldx)
+    _check("rpid_sketch_sparse_sign", s)
+    return X
+
+
+class CSC:
+    """A sparse m x n matrix in compressed sparse column form on the device
+    (colptr int64[n+1], rowidx int64[nnz], vals float64 or float32)."""
+
+    def __init__(self, colptr, rowidx, vals, m, n):
+        self.colptr = colptr.to(torch.int64).contiguous()
+        self.rowidx = rowidx.to(torch.int64).contiguous()
+        self.vals = vals.contiguous()
+        self.m, self.n = int(m), int(n)
+        self.nnz = int(self.rowidx.numel())
+
+    def args(self):
+        return (self.colptr.data_ptr(), self.rowidx.data_ptr(), self.vals.data_ptr(), dtype_code(self.vals),
+                self.m, self.n, self.nnz)
+
+
+def rpid_sketch_csc(ctx: Context, A: CSC, Gamma: torch.Tensor) -> torch.Tensor:
+    """X = Gamma A for a CSC matrix A; Gamma l x m of A's value type."""
+    pg, l, m2, ldg = colmajor(Gamma)
+    if m2 != A.m or Gamma.dtype != A.vals.dtype:
+        raise ValueError("Gamma must be l x m with A's value type")
+    X = empty_colmajor(l, A.n, A.vals.dtype, Gamma.device)
+    px, _, _, ldx = colmajor(X)
+    _check("rpid_sketch_csc", lib().rpid_sketch_csc(ctx.handle, *A.args(), pg, ldg, l, px, ldx))
+    return X
+
+
+def rpid_sketch_csc_sparse_sign(ctx: Context, A: CSC, rows: torch.Tensor, signs: torch.Tensor, l: int,
+                                scale: float) -> torch.Tensor:
+    """X = scale * S A for a CSC matrix A and a sparse sign embedding S."""
+    if rows.dtype != torch.int32 or signs.dtype != torch.int8 or rows.shape != signs.shape or rows.shape[0] != A.m:
+        raise ValueError("rows (int32) and signs (int8) must be m x zeta")
+    rows, signs = rows.contiguous(), signs.contiguous()
+    X = empty_colmajor(l, A.n, A.vals.dtype, A.vals.device)
+    px, _, _, ldx = colmajor(X)
+    s = lib().rpid_sketch_csc_sparse_sign(ctx.handle, *A.args(), rows.data_ptr(), signs.data_ptr(), rows.shape[1],
+                                          l, float(scale), px, ldx)
+    _check("rpid_sketch_csc_sparse_sign", s)
+    return X
+
+
+def rpid_csc_gather(ctx: Context, A: CSC, J=None) -> torch.Tensor:
+    """Dense C = A(:, J) (m x k), or all of A when J is None."""
+    k = A.n if J is None else int(J.numel())
+    C = empty_colmajor(A.m, k, A.vals.dtype, A.vals.device)
+    pc, _, _, ldc = colmajor(C)
+    s = lib().rpid_csc_gather(ctx.handle, *A.args(), k, J.data_ptr() if J is not None else None, pc, ldc)
+    _check("rpid_csc_gather", s)
+    return C
 
 
 def rpid_select_columns_cpqr(ctx: Context, X: torch.Tensor, k: int, sync: bool = True):

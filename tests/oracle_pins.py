@@ -547,3 +547,56 @@ def pin_cpqr_ties(O, seed=54, l=6, n=14):
 
 
 ALL_PINS += [pin_cpqr_ties]
+
+
+def pin_sparse_sign(O, seed=55, m=9, n=5, l=6, zeta=3):
+    """The sparse sign embedding: every column has exactly zeta entries +-1
+    at distinct rows (the draws of the inputs generator); its sketch equals
+    the sum of signed rows of A written out term by term; over many draws
+    E[S^T S] / zeta = I (the embedding's isometry in expectation)."""
+    rng = np.random.default_rng(seed)
+    rows, signs = inputs.sparse_sign_draws(rng, m, l, zeta)
+    S = O.sparse_sign_matrix(rows, signs, l)
+    assert S.shape == (l, m)
+    assert np.all(np.sum(S != 0, axis=0) == zeta) and np.all(np.abs(S[S != 0]) == 1.0)
+    a = rng.integers(-4, 5, (m, n)).astype(float)
+    X = O.sketch_sparse_sign(a, rows, signs, l, 0.5)
+    for r in range(l):
+        for j in range(n):
+            ref = 0.0
+            for i in range(m):
+                for s_ in range(zeta):
+                    if rows[i, s_] == r:
+                        ref += 0.5 * signs[i, s_] * a[i, j]
+            assert X[r, j] == ref
+    acc = np.zeros((m, m))
+    reps = 400
+    for _ in range(reps):
+        rr, ss = inputs.sparse_sign_draws(rng, m, l, zeta)
+        S = O.sparse_sign_matrix(rr, ss, l)
+        acc += S.T @ S / zeta
+    acc /= reps
+    np.testing.assert_allclose(np.diag(acc), 1.0, rtol=0, atol=1e-12)
+    assert np.abs(acc - np.diag(np.diag(acc))).max() < 0.12
+
+
+def pin_csc(O, seed=56, m=30, n=20):
+    """CSC reconstruction against scipy's (an independent implementation),
+    the SNN generator's non-negativity and structure, and the CSC sketch
+    against the dense product."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    s = np.array([2.0, 1.0, 0.5, 0.25])
+    colptr, rowidx, vals = inputs.snn_csc(rng, m, n, s, 0.2)
+    A = O.csc_dense(colptr, rowidx, vals, m, n)
+    ref = sp.csc_matrix((vals, rowidx, colptr), shape=(m, n)).toarray()
+    assert np.array_equal(A, ref)
+    assert np.all(vals > 0) and colptr[-1] == len(vals)
+    assert all(np.all(np.diff(rowidx[colptr[j]:colptr[j + 1]]) > 0) for j in range(n))
+    assert np.linalg.matrix_rank(A) <= len(s)
+    G = rng.standard_normal((5, m))
+    np.testing.assert_allclose(O.sketch_csc(colptr, rowidx, vals, m, n, G), G @ ref, rtol=1e-13, atol=1e-13)
+
+
+ALL_PINS += [pin_sparse_sign, pin_csc]

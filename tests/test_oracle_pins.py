@@ -76,6 +76,12 @@ MUTANTS = {
     "CPQR update without beta": ("S[t:, cols] -= beta * np.outer(v, d)", "S[t:, cols] -= np.outer(v, d)"),
     "CPQR Z from the transposed R_11": ("Z = sla.solve_triangular(R[:k, J], R[:k, :], lower=False)",
                                         "Z = sla.solve_triangular(R[:k, J].T, R[:k, :], lower=True)"),
+    "sparse sign entry at the wrong row": ("            G[rows[i, s_], i] = float(signs[i, s_])",
+                                           "            G[(rows[i, s_] + 1) % l, i] = float(signs[i, s_])"),
+    "sparse sign sketch without the scale": ("return float(scale) * (sparse_sign_matrix(rows, signs, l) @ _f64(A))",
+                                             "return sparse_sign_matrix(rows, signs, l) @ _f64(A)"),
+    "CSC entries transposed": ("            A[int(rowidx[p]), j] = float(vals[p])",
+                               "            A[int(rowidx[p]) % n, j % m] = float(vals[p])"),
     "row ID residual with C instead of R": ('out["rowid"] = nrm(A - _f64(W) @ R) / na',
                                             'out["rowid"] = nrm(A - _f64(W) @ R[:, ::-1]) / na'),
 }
