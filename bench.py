@@ -273,7 +273,7 @@ def cpqr_report(torch, R, ctx, A, Om, plain):
 
 def sparse_report(torch, R, ctx, A, Om):
     """Sparse and structured sketches (Sec. 2.2): the sparse sign embedding
-    (zeta = 8, scale 1/sqrt(8)) on the main dense input, and the CSC sketch of
+    (zeta = 8, scale 1/sqrt(8)) and the SRTT on the main dense input, and the CSC sketch of
     an SNN matrix (eq. snn-def) 65536 x 65536, r = 400, s_i = 2/i (i <= 100)
     then 1/i, x_i and y_i with 0.1 % nonzeros (FP32 values, l = 272, Gaussian
     and sparse sign embeddings), followed by Rand-LUPP's column selection."""
@@ -298,6 +298,9 @@ def sparse_report(torch, R, ctx, A, Om):
     rows_d, signs_d = torch.from_numpy(rows).cuda(), torch.from_numpy(signs).cuda()
     _, ms_ss_dense = timed(lambda: R.rpid_sketch_sparse_sign(ctx, A, rows_d, signs_d, L, 8 ** -0.5))
     _, ms_gauss_dense = timed(lambda: R.rpid_sketch(ctx, A, Om))
+    perm, phi, sel = inputs.srtt_draws(rng, m, L)
+    pd, fd, sd = torch.from_numpy(perm).cuda(), torch.from_numpy(phi).cuda(), torch.from_numpy(sel).cuda()
+    _, ms_srtt_dense = timed(lambda: R.rpid_sketch_srtt(ctx, A, pd, fd, sd))
     ms_ = 65536
     i = np.arange(1, 401, dtype=np.float64)
     sv = np.where(i <= 100, 2.0 / i, 1.0 / i)
@@ -309,7 +312,7 @@ def sparse_report(torch, R, ctx, A, Om):
     _, ms_csc_ss = timed(lambda: R.rpid_sketch_csc_sparse_sign(ctx, Ac, torch.from_numpy(r2).cuda(),
                                                                torch.from_numpy(s2).cuda(), L, 8 ** -0.5))
     (J, _, _, _, _, _), ms_sel = timed(lambda: R.rpid_select_columns(ctx, X, K, sync=False), reps=3)
-    return {"sparse_sign_dense_ms": ms_ss_dense, "gaussian_dense_ms": ms_gauss_dense,
+    return {"sparse_sign_dense_ms": ms_ss_dense, "gaussian_dense_ms": ms_gauss_dense, "srtt_dense_ms": ms_srtt_dense,
             "snn65536_nnz": int(len(va)), "csc_gaussian_sketch_ms": ms_csc, "csc_sparse_sign_sketch_ms": ms_csc_ss,
             "csc_select_columns_ms": ms_sel,
             "csc_gaussian_gflops": 2.0 * len(va) * L / (ms_csc * 1e-3) / 1e9}

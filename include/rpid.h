@@ -204,6 +204,24 @@ int rpid_sketch_sparse_sign(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t
                             int64_t l, double scale, void* X, rpid_dtype x_t, int64_t ldx);
 
 /*
+ * SRTT embedding (Sec. 2.2, second embedding) with the discrete Hartley
+ * transform: Gamma = sqrt(m / l) Pi_{m->l} T Phi Pi_{m->m}, i.e.
+ * Gamma(r, perm[b]) = cas(2 pi sel[r] b / m) phi[b] / sqrt(l) with cas = cos +
+ * sin; X = Gamma A.  The draws are the caller's (device arrays):
+ *   perm  int32[m], a permutation of 0..m-1 ((Pi_{m->m} x)_b = x_perm[b])
+ *   phi   int8[m], +1 or -1 (the Rademacher signs of Phi)
+ *   sel   int32[l], l distinct rows of the transform (Pi_{m->l})
+ *   A, a_t, m, n, lda, X, x_t, ldx as for rpid_sketch; 1 <= l <= min(m, 1024)
+ * Only l rows of the transform are kept, so the embedding is formed
+ * explicitly (FP64 sincos, stored in A's type: BF16 rounds its entries) and
+ * applied by the dense MFMA sketch.  Entries of perm outside [0, m) leave
+ * their target columns of Gamma zero.
+ */
+int rpid_sketch_srtt(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                     const int32_t* perm, const int8_t* phi, const int32_t* sel, int64_t l, void* X,
+                     rpid_dtype x_t, int64_t ldx);
+
+/*
  * Sketch of a sparse A given in compressed sparse column form (the sparse
  * inputs of Sec. 5, e.g. eq. snn-def): X = Gamma A.
  *   colptr  int64[n + 1], rowidx int64[nnz], vals[nnz] of type v_t (F64 or

@@ -36,6 +36,9 @@ randomized pivoting algorithms for CUR and interpolative decompositions":
 * id_coeffs_cpqr    -- Z = R_11^{-1} R_top from that QR (Z = X_1^+ X).
 * sparse_sign_matrix, sketch_sparse_sign -- the sparse sign embedding of
                        Sec. 2.2 (zeta signed entries per column) and its sketch.
+* dht_matrix, srtt_matrix, sketch_srtt -- the subsampled randomized
+                       trigonometric transform of Sec. 2.2 with the discrete
+                       Hartley transform.
 * csc_dense, sketch_csc -- a matrix in compressed sparse column form (the
                        sparse inputs, eq. snn-def) and its sketch.
 
@@ -81,6 +84,9 @@ __all__ = [
     "sketch_sparse_sign",
     "csc_dense",
     "sketch_csc",
+    "dht_matrix",
+    "srtt_matrix",
+    "sketch_srtt",
     "NonFiniteInput",
 ]
 
@@ -545,3 +551,27 @@ def csc_dense(colptr, rowidx, vals, m, n):
 def sketch_csc(colptr, rowidx, vals, m, n, Gamma):
     """X = Gamma A for A given in compressed sparse column form."""
     return _f64(Gamma) @ csc_dense(colptr, rowidx, vals, m, n)
+
+
+def dht_matrix(m):
+    """The m x m unitary discrete Hartley transform, T(a, b) = cas(2 pi a b /
+    m) / sqrt(m) with cas = cos + sin (a, b = 0..m-1)."""
+    ab = np.outer(np.arange(m), np.arange(m)) % m
+    ang = 2.0 * np.pi * ab / m
+    return (np.cos(ang) + np.sin(ang)) / np.sqrt(m)
+
+
+def srtt_matrix(perm, phi, sel, m, l):
+    """Gamma = sqrt(m / l) Pi_{m->l} T Phi Pi_{m->m} (Sec. 2.2): (Pi_{m->m} x)_b
+    = x_{perm[b]}, Phi = diag(phi), T the DHT, (Pi_{m->l} z)_r = z_{sel[r]}."""
+    P = np.zeros((m, m))
+    P[np.arange(m), np.asarray(perm)] = 1.0
+    S = np.zeros((l, m))
+    S[np.arange(l), np.asarray(sel)] = 1.0
+    return np.sqrt(m / l) * (S @ dht_matrix(m) @ np.diag(np.asarray(phi, dtype=np.float64)) @ P)
+
+
+def sketch_srtt(A, perm, phi, sel, l):
+    """X = Gamma A with the SRTT embedding above."""
+    A = _f64(A)
+    return srtt_matrix(perm, phi, sel, A.shape[0], l) @ A

@@ -856,6 +856,46 @@ int rpid_sketch_sparse_sign(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t
   return scale_matrix<float>(ctx, l, n, (float*)X, ldx, (float)scale);
 }
 
+int rpid_sketch_srtt(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
+                     const int32_t* perm, const int8_t* phi, const int32_t* sel, int64_t l, void* X,
+                     rpid_dtype x_t, int64_t ldx) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (!perm) return -7;
+  if (!phi) return -8;
+  if (!sel) return -9;
+  if (l < 1 || l > 1024 || l > m) return -10;
+  if (!X) return -11;
+  if (ldx < l) return -13;
+  const bool f64 = a_t == RPID_F64 && x_t == RPID_F64;
+  const bool f32 = a_t == RPID_F32 && x_t == RPID_F32;
+  const bool bf = a_t == RPID_BF16 && x_t == RPID_F32;
+  if (!(f64 || f32 || bf)) return RPID_ERR_UNSUPPORTED;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  Carve cv;
+  const size_t o_inv = cv.take<int32_t>((size_t)m);
+  const size_t o_pt = cv.take<char>((size_t)m * l * esize(a_t));
+  const size_t ws_sk = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, ws_sk + sketch_workspace_bytes(ctx, m, n, l, f64 ? 8 : 4)));
+  int32_t* inv = ws_ptr<int32_t>(ctx, o_inv);
+  if (f64) {
+    double* pt = ws_ptr<double>(ctx, o_pt);
+    RPID_CHECK(build_srtt_t<double>(ctx, m, l, perm, phi, sel, inv, pt, m));
+    return sketch_f64(ctx, pt, m, (const double*)A, lda, m, n, l, (double*)X, ldx, ws_sk);
+  }
+  if (f32) {
+    float* pt = ws_ptr<float>(ctx, o_pt);
+    RPID_CHECK(build_srtt_t<float>(ctx, m, l, perm, phi, sel, inv, pt, m));
+    return sketch_f32(ctx, pt, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
+  }
+  uint16_t* pt = ws_ptr<uint16_t>(ctx, o_pt);
+  RPID_CHECK(build_srtt_t<uint16_t>(ctx, m, l, perm, phi, sel, inv, pt, m));
+  return sketch_bf16(ctx, pt, m, (const uint16_t*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
+}
+
 static int csc_args(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, const void* vals,
                     rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz) {
   if (!ctx) return -1;

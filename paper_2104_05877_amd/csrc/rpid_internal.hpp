@@ -139,6 +139,10 @@ int expand_sparse_sign(rpid_ctx ctx, int64_t m, int64_t l, int zeta, const int32
                        const int8_t* signs, TE* out, int64_t rs, int64_t cs, bool i_fast);
 template <typename T>
 int scale_matrix(rpid_ctx ctx, int64_t rows, int64_t cols, T* X, int64_t ldx, T scale);
+// The SRTT embedding transposed (m x l, ldp) in TE; inv is m int32 of scratch.
+template <typename TE>
+int build_srtt_t(rpid_ctx ctx, int64_t m, int64_t l, const int32_t* perm, const int8_t* phi,
+                 const int32_t* sel, int32_t* inv, TE* Pt, int64_t ldp);
 // X = Gamma A for a CSC matrix A (m x n, nnz stored entries); Gamma l x m.
 template <typename T>
 int csc_sketch(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,

@@ -7,6 +7,11 @@
 //    embedding expanded to exact +-1 entries (BF16, FP32 or FP64 alike), the
 //    scale applied to X afterwards; the O(nnz zeta) count of the definition
 //    pays off for sparse A, where the work is the nonzeros anyway.
+//  * The SRTT embedding (subsampled randomized trigonometric transform with
+//    the discrete Hartley transform) keeps l of the m transform rows, so on
+//    MFMA hardware it is again cheapest as a dense l x m embedding, built from
+//    its definition (sincos in FP64, stored in A's type) and fed to the dense
+//    sketch.
 //  * The CSC sketch X = Gamma A runs one workgroup per column of A: every
 //    thread keeps up to four rows of X(:, j) in registers and adds
 //    Gamma(:, i) a_ij for the column's nonzeros in order (deterministic), so
@@ -55,6 +60,61 @@ __global__ void scatter_signs_kernel(int64_t m, int64_t l, int zeta, const int32
     const int64_t i = e / zeta;
     const int32_t r = rows[e];
     if (r >= 0 && r < l) out[(int64_t)r * rs + i * cs] = sign_value<TE>(signs[e]);
+  }
+}
+
+// inv[perm[b]] = b for the entries of perm inside [0, m) (inv pre-filled with -1)
+__global__ void invert_perm_kernel(int64_t m, const int32_t* perm, int32_t* inv) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < m; b += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = perm[b];
+    if (i >= 0 && i < m) inv[i] = (int32_t)b;
+  }
+}
+__global__ void fill_i32_kernel(int64_t count, int32_t* p, int32_t v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+template <typename TE>
+__device__ __forceinline__ TE from_double(double v);
+template <>
+__device__ __forceinline__ double from_double<double>(double v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ float from_double<float>(double v) {
+  return (float)v;
+}
+template <>
+__device__ __forceinline__ uint16_t from_double<uint16_t>(double v) {  // BF16, round to nearest even
+  uint32_t u = __float_as_uint((float)v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// The SRTT embedding transposed, Pt(i, r) = Gamma(r, i) = cas(2 pi sel[r] b /
+// m) phi[b] / sqrt(l) with b = inv[i] the position that perm maps to row i
+// (zero where inv[i] < 0); i varies fastest, so the writes are contiguous.
+template <typename TE>
+__global__ void srtt_build_kernel(int64_t m, int64_t l, const int32_t* inv, const int8_t* phi,
+                                  const int32_t* sel, TE* Pt, int64_t ldp) {
+  const int64_t total = m * l;
+  const double two_pi_over_m = 6.283185307179586476925286766559 / (double)m;
+  const double rs = 1.0 / sqrt((double)l);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % m, r = e / m;
+    const int64_t b = inv[i];
+    double v = 0.0;
+    if (b >= 0) {
+      int64_t a = sel[r] % m;
+      if (a < 0) a += m;
+      const int64_t q = (a * b) % m;
+      double sn, cs;
+      sincos(two_pi_over_m * (double)q, &sn, &cs);
+      v = (cs + sn) * (double)phi[b] * rs;
+    }
+    Pt[i + r * ldp] = from_double<TE>(v);
   }
 }
 
@@ -147,6 +207,25 @@ template int expand_sparse_sign<float>(rpid_ctx, int64_t, int64_t, int, const in
                                        const int8_t*, float*, int64_t, int64_t, bool);
 template int expand_sparse_sign<uint16_t>(rpid_ctx, int64_t, int64_t, int, const int32_t*,
                                           const int8_t*, uint16_t*, int64_t, int64_t, bool);
+
+template <typename TE>
+int build_srtt_t(rpid_ctx ctx, int64_t m, int64_t l, const int32_t* perm, const int8_t* phi,
+                 const int32_t* sel, int32_t* inv, TE* Pt, int64_t ldp) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(m)), dim3(256), 0, ctx->stream, m, inv, -1);
+  RPID_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(invert_perm_kernel, dim3(grid_for(m)), dim3(256), 0, ctx->stream, m, perm, inv);
+  RPID_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL((srtt_build_kernel<TE>), dim3(grid_for(m * l)), dim3(256), 0, ctx->stream, m, l, inv, phi,
+                     sel, Pt, ldp);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+template int build_srtt_t<double>(rpid_ctx, int64_t, int64_t, const int32_t*, const int8_t*, const int32_t*,
+                                  int32_t*, double*, int64_t);
+template int build_srtt_t<float>(rpid_ctx, int64_t, int64_t, const int32_t*, const int8_t*, const int32_t*,
+                                 int32_t*, float*, int64_t);
+template int build_srtt_t<uint16_t>(rpid_ctx, int64_t, int64_t, const int32_t*, const int8_t*, const int32_t*,
+                                    int32_t*, uint16_t*, int64_t);
 
 template <typename T>
 int scale_matrix(rpid_ctx ctx, int64_t rows, int64_t cols, T* X, int64_t ldx, T scale) {

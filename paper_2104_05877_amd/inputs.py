@@ -19,6 +19,9 @@ matrices stand in for them, with spectra controlled exactly):
 * ``sparse_sign_draws``: the random draws of a sparse sign embedding (Section
   2.2): for each of its m columns, zeta distinct row coordinates uniform over
   the l rows and zeta independent signs.
+* ``srtt_draws``: the random draws of an SRTT embedding (Section 2.2): a
+  permutation of the m rows, m Rademacher signs and l distinct rows of the
+  m x m transform.
 * ``snn_csc``: a sparse non-negative (SNN) matrix sum_i s_i x_i y_i^T with
   sparse non-negative x_i, y_i (eq. snn-def), in compressed sparse column
   form.  The paper leaves the sparsity of x_i, y_i open: here each x_i
@@ -271,3 +274,12 @@ def snn_csc(rng: np.random.Generator, m: int, n: int, s: np.ndarray, rho: float)
         vals.extend(d[k] for k in keys)
         colptr[j + 1] = colptr[j] + len(keys)
     return colptr, np.array(rowidx, dtype=np.int64), np.array(vals, dtype=np.float64)
+
+
+def srtt_draws(rng: np.random.Generator, m: int, l: int):
+    """perm (int32[m], a uniform permutation), phi (int8[m], +-1) and sel
+    (int32[l], l distinct rows out of m, uniform)."""
+    perm = rng.permutation(m).astype(np.int32)
+    phi = np.where(rng.random(m) < 0.5, -1, 1).astype(np.int8)
+    sel = rng.choice(m, l, replace=False).astype(np.int32)
+    return perm, phi, sel

@@ -51,6 +51,7 @@ _SIGS = {
     "rpid_select_columns_cpqr": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _P]),
     "rpid_sketch_sparse_sign": (_i, [_P, _P, _i, _I, _I, _I, _P, _P, _I, _I, ctypes.c_double, _P, _i, _I]),
     "rpid_sketch_csc": (_i, [_P, _P, _P, _P, _i, _I, _I, _I, _P, _I, _I, _P, _I]),
+    "rpid_sketch_srtt": (_i, [_P, _P, _i, _I, _I, _I, _P, _P, _P, _I, _P, _i, _I]),
     "rpid_sketch_csc_sparse_sign": (_i, [_P, _P, _P, _P, _i, _I, _I, _I, _P, _P, _I, _I, ctypes.c_double,
                                          _P, _I]),
     "rpid_csc_gather": (_i, [_P, _P, _P, _P, _i, _I, _I, _I, _I, _P, _P, _I]),
@@ -271,6 +272,26 @@ def rpid_sketch_sparse_sign(ctx: Context, A: torch.Tensor, rows: torch.Tensor, s
     s = lib().rpid_sketch_sparse_sign(ctx.handle, pa, dtype_code(A), m, n, lda, rows.data_ptr(), signs.data_ptr(),
                                       rows.shape[1], l, float(scale), px, dtype_code(X), ldx)
     _check("rpid_sketch_sparse_sign", s)
+    return X
+
+
+def rpid_sketch_srtt(ctx: Context, A: torch.Tensor, perm: torch.Tensor, phi: torch.Tensor,
+                     sel: torch.Tensor) -> torch.Tensor:
+    """X = Gamma A with the SRTT embedding given by perm (int32[m]), phi
+    (int8[m]) and sel (int32[l]); BF16 A gives an FP32 X."""
+    pa, m, n, lda = colmajor(A)
+    if perm.dtype != torch.int32 or phi.dtype != torch.int8 or sel.dtype != torch.int32:
+        raise ValueError("perm int32, phi int8, sel int32")
+    if perm.numel() != m or phi.numel() != m:
+        raise ValueError("perm and phi must have m entries")
+    l = int(sel.numel())
+    perm, phi, sel = perm.contiguous(), phi.contiguous(), sel.contiguous()
+    out_dtype = torch.float32 if A.dtype == torch.bfloat16 else A.dtype
+    X = empty_colmajor(l, n, out_dtype, A.device)
+    px, _, _, ldx = colmajor(X)
+    s = lib().rpid_sketch_srtt(ctx.handle, pa, dtype_code(A), m, n, lda, perm.data_ptr(), phi.data_ptr(),
+                               sel.data_ptr(), l, px, dtype_code(X), ldx)
+    _check("rpid_sketch_srtt", s)
     return X
 
 

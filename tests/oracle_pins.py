@@ -600,3 +600,30 @@ def pin_csc(O, seed=56, m=30, n=20):
 
 
 ALL_PINS += [pin_sparse_sign, pin_csc]
+
+
+def pin_srtt(O, seed=57, m=48, l=12, n=7):
+    """The DHT is symmetric, orthogonal and its own inverse, and equals
+    Re(F) - Im(F) for the DFT matrix F (numpy's FFT, an independent route);
+    the SRTT embedding has orthogonal rows of squared norm m / l
+    (Gamma Gamma^T = (m / l) I) and its sketch matches a term-by-term sum."""
+    T = O.dht_matrix(m)
+    np.testing.assert_allclose(T, T.T, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(T @ T, np.eye(m), rtol=0, atol=1e-12)
+    F = np.fft.fft(np.eye(m)) / np.sqrt(m)
+    np.testing.assert_allclose(T, F.real - F.imag, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(seed)
+    perm, phi, sel = inputs.srtt_draws(rng, m, l)
+    G = O.srtt_matrix(perm, phi, sel, m, l)
+    np.testing.assert_allclose(G @ G.T, (m / l) * np.eye(l), rtol=0, atol=1e-11)
+    a = rng.standard_normal((m, n))
+    X = O.sketch_srtt(a, perm, phi, sel, l)
+    r, j = 5, 3
+    ref = 0.0
+    for b in range(m):
+        ang = 2.0 * np.pi * ((int(sel[r]) * b) % m) / m
+        ref += np.sqrt(m / l) * (np.cos(ang) + np.sin(ang)) / np.sqrt(m) * phi[b] * a[perm[b], j]
+    assert abs(X[r, j] - ref) <= 1e-12 * np.sqrt(m) * np.abs(a).max()
+
+
+ALL_PINS += [pin_srtt]

@@ -162,3 +162,55 @@ def test_sparse_argument_errors(R, ctx):
     with pytest.raises(R.RpidError) as e:  # non-positive scale
         R.rpid_sketch_sparse_sign(ctx, A, rows, signs, 16, 0.0)
     assert e.value.status == -11
+
+
+@pytest.mark.parametrize("m,n,l,seed", [(1024, 700, 64, 11), (1000, 513, 100, 12)])
+@pytest.mark.parametrize("dt", ["float64", "float32", "bfloat16"])
+def test_srtt_against_oracle(R, ctx, m, n, l, seed, dt):
+    """The SRTT sketch (DHT, random permutation, signs and row selection)
+    against the oracle's explicit Gamma = sqrt(m/l) S T Phi P on the stored
+    A: within (2m + 8) u |Gamma| |A|, plus 2^-8 |Gamma| |A| in BF16, whose
+    embedding entries are rounded to BF16."""
+    say("srtt", dt, m, n, l)
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n))
+    perm, phi, sel = inputs.srtt_draws(rng, m, l)
+    Ad = dev(A, getattr(torch, dt))
+    a_s = host(Ad)
+    X = R.rpid_sketch_srtt(ctx, Ad, torch.from_numpy(perm).cuda(), torch.from_numpy(phi).cuda(),
+                           torch.from_numpy(sel).cuda())
+    G = O.srtt_matrix(perm, phi, sel, m, l)
+    ref = G @ a_s
+    u = 2.0**-53 if dt == "float64" else 2.0**-24
+    mag = np.abs(G) @ np.abs(a_s)
+    bound = (2 * m + 8) * u * mag + (2.0**-8 * mag if dt == "bfloat16" else 0.0) + 1e-300
+    err = np.abs(host(X) - ref)
+    say("max err/bound", float((err / bound).max()))
+    assert np.all(err <= bound)
+
+
+def test_srtt_rand_lupp_fp64(R, ctx):
+    """Rand-LUPP on an SRTT sketch (FP64): pivots equal the oracle's on the
+    same sketch values up to the first near-tie and the ID residual matches
+    to 1e-9 relative."""
+    m, n, k, l = 1024, 900, 40, 50
+    A, _ = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 13)
+    perm, phi, sel = inputs.srtt_draws(np.random.default_rng(14), m, l)
+    Ad = dev(A)
+    X = R.rpid_sketch_srtt(ctx, Ad, torch.from_numpy(perm).cuda(), torch.from_numpy(phi).cuda(),
+                           torch.from_numpy(sel).cuda())
+    J, Lf, Uf, _, keff, st = R.rpid_select_columns(ctx, X, k)
+    assert st == 0
+    f = O.lupp_colwise(host(X), k, gaps=True)
+    fc = int(np.argmax(f["gap"] < 1e-9)) if (f["gap"] < 1e-9).any() else k
+    assert np.array_equal(J.cpu().numpy()[:fc], f["J"][:fc])
+    Z, _ = R.rpid_id_coeffs(ctx, X, k, J, Lf, Uf)
+    rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, J, Z=Z)
+    Xo = O.sketch_srtt(A, perm, phi, sel, l)
+    fo = O.lupp_colwise(Xo, k)
+    ro = O.residuals(A, fo["J"], Z=O.id_coeffs(Xo, fo["J"], k), only=("id",))["id"]
+    say("srtt id residual gpu", rid, "oracle", ro, "matched", fc)
+    if fc == k:
+        assert abs(rid - ro) <= 1e-9 * ro
+    else:
+        assert rid <= 1.05 * ro

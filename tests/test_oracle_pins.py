@@ -82,6 +82,8 @@ MUTANTS = {
                                              "return sparse_sign_matrix(rows, signs, l) @ _f64(A)"),
     "CSC entries transposed": ("            A[int(rowidx[p]), j] = float(vals[p])",
                                "            A[int(rowidx[p]) % n, j % m] = float(vals[p])"),
+    "DHT with cos - sin": ("return (np.cos(ang) + np.sin(ang)) / np.sqrt(m)", "return (np.cos(ang) - np.sin(ang)) / np.sqrt(m)"),
+    "SRTT permutation applied inverted": ("P[np.arange(m), np.asarray(perm)] = 1.0", "P[np.asarray(perm), np.arange(m)] = 1.0"),
     "row ID residual with C instead of R": ('out["rowid"] = nrm(A - _f64(W) @ R) / na',
                                             'out["rowid"] = nrm(A - _f64(W) @ R[:, ::-1]) / na'),
 }
