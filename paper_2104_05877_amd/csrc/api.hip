@@ -395,12 +395,22 @@ int rpid_create(rpid_ctx* out, int device, void* hip_stream) {
 
 int rpid_destroy(rpid_ctx ctx) {
   if (!ctx) return -1;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
-  if (ctx->ws) hipFree(ctx->ws);
-  if (ctx->host_status) hipHostFree(ctx->host_status);
+  // every release is attempted; the first failure is reported.  The uncached
+  // exchange buffer stays allocated until the process ends (device memory of
+  // that kind is never freed once a kernel has read it).
+  hipError_t e = hipSetDevice(ctx->device);
+  const hipError_t e1 = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = e1;
+  if (ctx->ws) {
+    const hipError_t e2 = hipFree(ctx->ws);
+    if (e == hipSuccess) e = e2;
+  }
+  if (ctx->host_status) {
+    const hipError_t e3 = hipHostFree(ctx->host_status);
+    if (e == hipSuccess) e = e3;
+  }
   delete ctx;
-  return RPID_OK;
+  return e == hipSuccess ? RPID_OK : RPID_ERR_HIP;
 }
 
 int rpid_set_stream(rpid_ctx ctx, void* hip_stream) {
