@@ -263,8 +263,13 @@ def cpqr_report(torch, R, ctx, A, Om, plain):
     (J, Rf, diag, _, _), ms_qr = timed(lambda: R.rpid_select_columns_cpqr(ctx, X, K, sync=False))
     Z, ms_z = timed(lambda: R.rpid_id_coeffs_cpqr(ctx, K, J, Rf))
     rid = R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, J, Z=Z)
+    # Rand-LUPP's pivots with the least-squares Z over all l rows (the same Z
+    # formula as CPQR's), for a like-for-like comparison of the pivots
+    Jl, _, _, _, _, _ = R.rpid_select_columns(ctx, X, K)
+    Zls, ms_ls = timed(lambda: R.rpid_id_coeffs_ls(ctx, X, K, Jl))
+    rid_ls = R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, Jl, Z=Zls)
     out = {"cpqr_ms": ms_qr, "cpqr_us_per_pivot": ms_qr * 1e3 / K, "id_coeffs_cpqr_ms": ms_z,
-           "residual_id_cpqr": rid}
+           "residual_id_cpqr": rid, "residual_id_lupp_least_squares_z": rid_ls, "id_coeffs_ls_ms": ms_ls}
     if plain is not None:
         out.update({"lupp_select_columns_ms": plain["per_call_ms"]["select_columns"],
                     "lupp_id_coeffs_ms": plain["per_call_ms"]["id_coeffs"], "residual_id_lupp": plain["rid"]})

@@ -289,6 +289,20 @@ int rpid_id_coeffs_cpqr(rpid_ctx ctx, rpid_dtype r_t, int64_t k, int64_t n, cons
                         const void* Rf, int64_t ldr, double* Z, int64_t ldz);
 
 /*
+ * ID coefficients by least squares over all l rows of the sketch: Z = X_1^+ X
+ * with X_1 = X(:, J) (l x k), Sec. 4's estimate of C^+ A taken literally for
+ * l > k (rpid_id_coeffs uses the first k rows only; both agree for l = k).
+ * Formed in FP64 by two Cholesky-QR passes of X_1 (X_1 = Q R) and
+ * Z = R^{-1} (Q^T X), then Z(:, J) = I.
+ *   X, x_t (F64 or F32), l, n, ldx, k, J as for rpid_id_coeffs (any pivots)
+ *   Z      k x n FP64, ldz >= k (output)
+ * Returns RPID_ERR_BREAKDOWN if a Cholesky factorisation meets a
+ * non-positive pivot (X_1 numerically rank deficient); synchronises.
+ */
+int rpid_id_coeffs_ls(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n, int64_t ldx,
+                      int64_t k, const int64_t* J, double* Z, int64_t ldz);
+
+/*
  * S4 -- ID coefficients from the pivoted sketch (Sec. 4: C^+ A ~ X_1^+ X):
  * Z = X_1^{-1} X_k with X_k = X(0:k, :), X_1 = X_k(:, J), so that A ~ A(:, J) Z.
  * Computed from the LUPP factors: Z(:, J[t]) = e_t and, for j not in J,

@@ -15,6 +15,7 @@ randomized pivoting algorithms for CUR and interpolative decompositions":
                        eq. (def_LUPP), Alg. 2 step 3.
 * id_coeffs         -- ID coefficients from the pivoted sketch, Sec. 4:
                        C^+ A is estimated by X_1^+ X (X_1 = X(:, J_s)).
+* id_coeffs_ls      -- the same estimate by least squares over all l rows.
 * eta               -- the a-posteriori factor of Theorem 1:
                        eta = || [-X_1^+ X_2 ; I] ||_2 = sqrt(1 + ||Z_rest||_2^2).
 * lupp_rowwise      -- Alg. 2 step 4, row-wise LUPP on C = A(:, J_s).
@@ -68,6 +69,7 @@ __all__ = [
     "lupp_colwise",
     "lupp_rowwise",
     "id_coeffs",
+    "id_coeffs_ls",
     "eta",
     "cur_u",
     "residuals",
@@ -266,6 +268,19 @@ def id_coeffs(X, J, k=None):
     J = J[:k]
     Xk = X[:k, :]
     Z = np.linalg.solve(Xk[:, J], Xk)
+    Z[:, J] = np.eye(k)
+    return Z
+
+
+def id_coeffs_ls(X, J, k=None):
+    """Z = X(:, J)^+ X by least squares over all l rows of the sketch (Sec.
+    4's X_1^+ X for l > k); Z(:, J) = I."""
+    X = _f64(X)
+    J = np.asarray(J, dtype=np.int64)
+    if k is None:
+        k = J.shape[0]
+    J = J[:k]
+    Z = np.linalg.lstsq(X[:, J], X, rcond=None)[0]
     Z[:, J] = np.eye(k)
     return Z
 

@@ -1051,6 +1051,82 @@ int rpid_id_coeffs_cpqr(rpid_ctx ctx, rpid_dtype r_t, int64_t k, int64_t n, cons
 }
 
 // ---------------------------------------------------------------------------
+// Z = X_1^+ X over all l rows of the sketch (X_1 = X(:, J)), by a
+// Cholesky-QR2 of X_1: X_1 = Q R, Z = R^{-1} (Q^T X); Z(:, J) = I.
+int rpid_id_coeffs_ls(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n, int64_t ldx,
+                      int64_t k, const int64_t* J, double* Z, int64_t ldz) {
+  if (!ctx) return -1;
+  if (!X) return -2;
+  if (!is_lupp_type(x_t)) return -3;
+  if (l < 1) return -4;
+  if (n < 1) return -5;
+  if (ldx < l) return -6;
+  if (k < 1 || k > l || k > n || k > 1024) return -7;
+  if (!J) return -8;
+  if (!Z) return -9;
+  if (ldz < k) return -10;
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  const int64_t kk = k * k;
+  Carve cv;
+  const size_t o_status = cv.take<int64_t>(8);
+  const size_t o_X64 = x_t == RPID_F64 ? 0 : cv.take<double>((size_t)l * n);
+  const size_t o_X1 = cv.take<double>((size_t)l * k);
+  const size_t o_Q = cv.take<double>((size_t)l * k);
+  const size_t o_G = cv.take<double>((size_t)2 * kk);
+  const size_t o_W = cv.take<double>((size_t)2 * kk);
+  const size_t o_Ri = cv.take<double>((size_t)kk);
+  const size_t o_Y = cv.take<double>((size_t)k * n);
+  const size_t o_tmp = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, o_tmp + (size_t)64 * kk * sizeof(double) + 4096));
+  int64_t* status_dev = ws_ptr<int64_t>(ctx, o_status);
+  const double* X64 = (const double*)X;
+  int64_t ld64 = ldx;
+  if (x_t != RPID_F64) {
+    double* Xc = ws_ptr<double>(ctx, o_X64);
+    RPID_CHECK(convert_matrix<float, double>(ctx, l, n, (const float*)X, ldx, Xc, l));
+    X64 = Xc;
+    ld64 = l;
+  }
+  double* X1 = ws_ptr<double>(ctx, o_X1);
+  double* Q = ws_ptr<double>(ctx, o_Q);
+  double* G = ws_ptr<double>(ctx, o_G);
+  double* W = ws_ptr<double>(ctx, o_W);
+  double* Ri = ws_ptr<double>(ctx, o_Ri);
+  double* Y = ws_ptr<double>(ctx, o_Y);
+  RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(status_dev), 2, 0ull));
+  RPID_CHECK(gather_columns<double, double>(ctx, l, k, X64, ld64, n, J, X1, l));
+  // two Cholesky-QR passes: X1 -> Q (R1^{-1} in W), Q -> X1 (R2^{-1} in W + kk)
+  const double* in = X1;
+  double* out = Q;
+  for (int pass = 0; pass < 2; ++pass) {
+    double* Gp = G + pass * kk;
+    double* Wp = W + pass * kk;
+    RPID_CHECK(dgemm(ctx, true, false, k, k, l, 1.0, in, l, in, l, 0.0, Gp, k, o_tmp));
+    if (sweep_supported(k)) {
+      RPID_CHECK(chol_inverse_batched(ctx, 1, k, Gp, k, kk, Wp, k, kk, status_dev + pass, o_tmp));
+    } else {
+      RPID_CHECK(cholesky_batched(ctx, 1, k, Gp, k, kk, status_dev + pass));
+      RPID_CHECK(tri_inverse(ctx, k, Gp, k, false, false, Wp, k, o_tmp));
+    }
+    RPID_CHECK(dgemm(ctx, false, false, l, k, k, 1.0, in, l, Wp, k, 0.0, out, l, o_tmp));
+    in = out;
+    out = X1;
+  }
+  // in = Q (orthonormal), R^{-1} = R1^{-1} R2^{-1}; Z = R^{-1} (Q^T X)
+  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, W, k, W + kk, k, 0.0, Ri, k, o_tmp));
+  RPID_CHECK(dgemm(ctx, true, false, k, n, l, 1.0, in, l, X64, ld64, 0.0, Y, k, o_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, k, n, k, 1.0, Ri, k, Y, k, 0.0, Z, ldz, o_tmp));
+  RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
+  int64_t st[2] = {0, 0};
+  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                ctx->stream));
+  RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  st[0] = ctx->host_status[0];
+  st[1] = ctx->host_status[1];
+  return (st[0] != 0 || st[1] != 0) ? RPID_ERR_BREAKDOWN : RPID_OK;
+}
+
+// ---------------------------------------------------------------------------
 int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
                    int64_t ldx, int64_t k, const int64_t* J, const void* Lf, int64_t ldl,
                    const void* Uf, int64_t ldu, double* Z, int64_t ldz, int refine_steps,

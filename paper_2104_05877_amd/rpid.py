@@ -56,6 +56,7 @@ _SIGS = {
                                          _P, _I]),
     "rpid_csc_gather": (_i, [_P, _P, _P, _P, _i, _I, _I, _I, _I, _P, _P, _I]),
     "rpid_id_coeffs_cpqr": (_i, [_P, _i, _I, _I, _P, _P, _I, _P, _I]),
+    "rpid_id_coeffs_ls": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I]),
     "rpid_sketch_fp8": (_i, [_P, _P, _I, _I, _I, _P, _I, _I, _P, _I]),
     "rpid_select_columns": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, ctypes.POINTER(_I)]),
     "rpid_id_coeffs": (
@@ -368,6 +369,15 @@ def rpid_id_coeffs_cpqr(ctx, k, J, Rf):
     s = lib().rpid_id_coeffs_cpqr(ctx.handle, dtype_code(Rf), k, n, J.data_ptr(), pr, ldr, Z.data_ptr(),
                                   Z.stride(1))
     _check("rpid_id_coeffs_cpqr", s)
+    return Z
+
+
+def rpid_id_coeffs_ls(ctx, X, k, J):
+    """Z = X(:, J)^+ X by least squares over all l rows (k x n FP64)."""
+    px, l, n, ldx = colmajor(X)
+    Z = empty_colmajor(k, n, torch.float64, X.device)
+    _check("rpid_id_coeffs_ls", lib().rpid_id_coeffs_ls(ctx.handle, px, dtype_code(X), l, n, ldx, k, J.data_ptr(),
+                                                        Z.data_ptr(), Z.stride(1)))
     return Z
 
 

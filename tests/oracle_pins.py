@@ -627,3 +627,24 @@ def pin_srtt(O, seed=57, m=48, l=12, n=7):
 
 
 ALL_PINS += [pin_srtt]
+
+
+def pin_id_coeffs_ls(O, seed=58, l=14, n=40, k=9):
+    """Least-squares Z over all l rows: its residual is orthogonal to the
+    columns X(:, J) (normal equations), it is no larger than that of the
+    first-k-rows Z, and for l = k both coincide."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((l, n))
+    J = O.lupp_colwise(X, k)["J"]
+    Z = O.id_coeffs_ls(X, J, k)
+    assert np.array_equal(Z[:, J], np.eye(k))
+    res = X - X[:, J] @ Z
+    assert np.abs(X[:, J].T @ res).max() <= 1e-12 * np.abs(X).max() ** 2 * l
+    Zk = O.id_coeffs(X, J, k)
+    assert np.linalg.norm(res) <= np.linalg.norm(X - X[:, J] @ Zk) * (1 + 1e-12)
+    Xs = X[:k, :]
+    Js = O.lupp_colwise(Xs, k)["J"]
+    np.testing.assert_allclose(O.id_coeffs_ls(Xs, Js, k), O.id_coeffs(Xs, Js, k), rtol=0, atol=1e-9)
+
+
+ALL_PINS += [pin_id_coeffs_ls]

@@ -146,3 +146,31 @@ def test_cpqr_errors(R, ctx):
     with pytest.raises(R.RpidError) as e:
         R.rpid_select_columns_cpqr(ctx, dev(np.ones((600, 700))), 4)
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("dt", ["float64", "float32"])
+def test_id_coeffs_ls_against_oracle(R, ctx, dt):
+    """Least-squares Z over all l rows for the LUPP pivots: against the
+    oracle's lstsq (FP64 within 1e-8 max|Z|), the ID residual within 1e-9
+    (FP64) or 1.05x (FP32), and no larger than the first-k-rows Z's."""
+    m, n, k, l = 1200, 1000, 40, 56
+    A, Om = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 22)
+    tdt = getattr(torch, dt)
+    Ad = dev(A, tdt)
+    X = R.rpid_sketch(ctx, Ad, dev(Om, tdt))
+    J, Lf, Uf, _, _, st = R.rpid_select_columns(ctx, X, k)
+    assert st == 0
+    Zls = R.rpid_id_coeffs_ls(ctx, X, k, J)
+    Zk, _ = R.rpid_id_coeffs(ctx, X, k, J, Lf, Uf, refine_steps=0 if dt == "float64" else 1)
+    r_ls = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, J, Z=Zls)
+    r_k = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, J, Z=Zk)
+    Xh, a_s, Jh = host(X), host(Ad), J.cpu().numpy()
+    Zo = O.id_coeffs_ls(Xh, Jh, k)
+    r_o = O.residuals(a_s, Jh, Z=Zo, only=("id",))["id"]
+    say(dt, "least-squares Z residual", r_ls, "oracle", r_o, "first-k-rows Z", r_k)
+    if dt == "float64":
+        np.testing.assert_allclose(host(Zls), Zo, rtol=0, atol=1e-8 * np.abs(Zo).max())
+        assert abs(r_ls - r_o) <= 1e-9 * r_o
+    else:
+        assert r_ls <= 1.05 * r_o
+    assert r_ls <= r_k * 1.001

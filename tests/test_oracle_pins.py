@@ -84,6 +84,8 @@ MUTANTS = {
                                "            A[int(rowidx[p]) % n, j % m] = float(vals[p])"),
     "DHT with cos - sin": ("return (np.cos(ang) + np.sin(ang)) / np.sqrt(m)", "return (np.cos(ang) - np.sin(ang)) / np.sqrt(m)"),
     "SRTT permutation applied inverted": ("P[np.arange(m), np.asarray(perm)] = 1.0", "P[np.asarray(perm), np.arange(m)] = 1.0"),
+    "least-squares Z over the first k rows only": ("    Z = np.linalg.lstsq(X[:, J], X, rcond=None)[0]",
+                                                    "    Z = np.linalg.lstsq(X[:k][:, J], X[:k], rcond=None)[0]"),
     "row ID residual with C instead of R": ('out["rowid"] = nrm(A - _f64(W) @ R) / na',
                                             'out["rowid"] = nrm(A - _f64(W) @ R[:, ::-1]) / na'),
 }
