@@ -206,20 +206,19 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   // (S5) C = A(:, J); (S6) row-wise LUPP on C gives I
   RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(I), (size_t)k, 0ull));
   RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, C64, m));
+  // the LUPP status goes to slot 4 and is read with the Cholesky statuses at
+  // the end (one host synchronisation per call): after a zero pivot the rest
+  // runs on the zero-filled tail of I, which only reads valid rows of A
+  int64_t* lupp_status = status_dev + 4;
   if (f64) {
     RPID_CHECK(lupp_panel<double>(ctx, C64, 1, m, m, k, I, ws_ptr<double>(ctx, o_Lc), m,
-                                  ws_ptr<double>(ctx, o_Uc), k, nullptr, o_tmp, status_dev));
+                                  ws_ptr<double>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
   } else {
     float* C32 = ws_ptr<float>(ctx, o_C32);
     RPID_CHECK(gather_columns<TA, float>(ctx, m, k, A, lda, n, J, C32, m));
     RPID_CHECK(lupp_panel<float>(ctx, C32, 1, m, m, k, I, ws_ptr<float>(ctx, o_Lc), m,
-                                 ws_ptr<float>(ctx, o_Uc), k, nullptr, o_tmp, status_dev));
+                                 ws_ptr<float>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
   }
-  int64_t st = 0;
-  RPID_CHECK(read_status(ctx, status_dev, &st));
-  if (st < 0) return (int)st;
-  if (k_eff) *k_eff = (st == 0) ? k : st - 1;
-  if (st > 0) return (int)st;
 
   // (S7) R^T = A(I, :)^T (n x k), orthonormal bases by Cholesky-QR2
   RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, ws_ptr<double>(ctx, o_W), k));
@@ -264,9 +263,13 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi + kk, k, Wi + 3 * kk, k, 0.0, Tr, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Tc, k, M, k, 0.0, Y, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, true, k, k, k, 1.0, Y, k, Tr, k, 0.0, U, ldu, o_tmp));
-  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 4 * sizeof(int64_t),
+  RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 5 * sizeof(int64_t),
                                 hipMemcpyDeviceToHost, ctx->stream));
   RPID_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  const int64_t st = ctx->host_status[4];
+  if (st < 0) return (int)st;
+  if (k_eff) *k_eff = (st == 0) ? k : st - 1;
+  if (st > 0) return (int)st;
   for (int b = 0; b < 4; ++b)
     if (ctx->host_status[b] != 0) return RPID_ERR_BREAKDOWN;
   return RPID_OK;
