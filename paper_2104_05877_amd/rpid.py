@@ -467,6 +467,49 @@ def rpid_mlp_loss(ctx, yhat, target, tau):
     return loss, dy
 
 
+def decompose_overlapped(ctx, ctx2, A, Omega, k, refine_steps=None):
+    """Alg. 2 end to end with both residuals, the two branches that follow
+    the column pivots run concurrently: Z and the ID residual on ctx2's
+    stream (from a worker thread; the library calls release the interpreter
+    lock), the CUR step and its residual on ctx's stream.  ctx2 needs its own
+    stream; the two contexts have separate workspaces, so the branches share
+    nothing but their read-only inputs.  The results are those of the
+    sequential order (the same kernels on the same inputs)."""
+    import threading
+
+    X = rpid_sketch(ctx, A, Omega)
+    if refine_steps is None:
+        refine_steps = 0 if X.dtype == torch.float64 else 1
+    J, Lf, Uf, diag, keff, st = rpid_select_columns(ctx, X, k)
+    out = dict(X=X, J=J, Lf=Lf, Uf=Uf, diag=diag, k_eff=keff, status=st)
+    if st != 0:
+        return out
+    ready = torch.cuda.Event()
+    ready.record(ctx.stream)
+    side = {}
+
+    def id_branch():
+        try:
+            ctx2.stream.wait_event(ready)
+            Z, _ = rpid_id_coeffs(ctx2, X, k, J, Lf, Uf, refine_steps=refine_steps)
+            side["Z"] = Z
+            side["rid"] = rpid_residual(ctx2, RESIDUAL_ID, A, k, J, Z=Z)
+        except Exception as e:  # noqa: BLE001 (re-raised in the caller's thread)
+            side["error"] = e
+
+    worker = threading.Thread(target=id_branch)
+    worker.start()
+    try:
+        I, U, keff_i, st_i = rpid_cur(ctx, A, k, J)
+        rcur = rpid_residual(ctx, RESIDUAL_CUR, A, k, J, I=I, U=U) if st_i == 0 else None
+    finally:
+        worker.join()
+    if "error" in side:
+        raise side["error"]
+    out.update(Z=side["Z"], I=I, U=U, status_I=st_i, residual_id=side["rid"], residual_cur=rcur)
+    return out
+
+
 def decompose(ctx, A, Omega, k, refine_steps=None, want_eta=False, want_cur=True):
     """The whole path: sketch, column LUPP, Z, and (optionally) CUR.  The
     LUPP runs in FP64 for FP64 storage and in FP32 otherwise."""

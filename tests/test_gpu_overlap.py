@@ -1,0 +1,42 @@
+"""GPU test of the overlapped decomposition: Z and the ID residual on a
+second context and stream, concurrent with the CUR step, give bitwise the
+outputs of the sequential order."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2104_05877_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dt", ["float64", "bfloat16"])
+def test_overlapped_equals_sequential(dt):
+    from paper_2104_05877_amd import rpid as R
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    print("[overlap]", dt, flush=True)
+    m, n, k, l = 2048, 1536, 64, 80
+    A, Om = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 31)
+    tdt = getattr(torch, dt)
+    Ad = inputs.torch_colmajor(A, tdt, "cuda")
+    Od = inputs.torch_colmajor(Om, tdt, "cuda")
+    ctx = R.Context(0)
+    ctx2 = R.Context(0, stream=torch.cuda.Stream(device=0))
+    try:
+        seq = R.decompose(ctx, Ad, Od, k)
+        rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, seq["J"], Z=seq["Z"])
+        rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, k, seq["J"], I=seq["I"], U=seq["U"])
+        for _ in range(3):  # repeated, with the side stream reused
+            ov = R.decompose_overlapped(ctx, ctx2, Ad, Od, k)
+            assert torch.equal(ov["J"], seq["J"]) and torch.equal(ov["I"], seq["I"])
+            assert torch.equal(ov["Z"], seq["Z"]) and torch.equal(ov["U"], seq["U"])
+            assert ov["residual_id"] == rid and ov["residual_cur"] == rcur
+    finally:
+        ctx2.close()
+        ctx.close()
+    assert np.isfinite(rid) and np.isfinite(rcur)
