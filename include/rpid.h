@@ -359,6 +359,17 @@ int rpid_residual(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_
                   const int64_t* I, const double* U, int64_t ldu, double* rel_fro);
 
 /*
+ * The same residual without a host synchronisation: sums[0] = ||A - P Q||_F^2
+ * and sums[1] = ||A||_F^2 (device FP64, caller-owned) are written on the
+ * context's stream; the relative residual is sqrt(sums[0] / sums[1]).  For
+ * overlapping it with other work on another stream.  Arguments as for
+ * rpid_residual; -15 if sums is NULL.
+ */
+int rpid_residual_sums(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                       int64_t lda, int64_t k, const int64_t* J, const double* Z, int64_t ldz,
+                       const int64_t* I, const double* U, int64_t ldu, double* sums);
+
+/*
  * Learned rank (not in the paper).  Features of the pivot-magnitude profile
  * of a sketch's LUPP: f_t = max(log10(diagU[t] / diagU[0]), -20), t < L;
  * entries t >= k_eff (zero pivots) are -20.  diagU is type x_t (F32/F64),

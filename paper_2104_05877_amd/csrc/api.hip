@@ -280,7 +280,7 @@ template <typename TA>
 static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, int64_t m,
                          int64_t n, int64_t lda, int64_t k, const int64_t* J, const double* Z,
                          int64_t ldz, const int64_t* I, const double* U, int64_t ldu,
-                         double* rel_fro) {
+                         double* rel_fro, double* sums_dev) {
   const bool bf = a_t == RPID_BF16;
   constexpr int kParts = 3;  // BF16 terms of an FP64 factor
   Carve cv;
@@ -293,7 +293,8 @@ static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, i
   const size_t o_part = cv.take<double>(residual_partials(m, n, bf) + 16);
   const size_t o_tmp = cv.off;
   RPID_CHECK(ensure_workspace(ctx, o_tmp + (size_t)64 * k * k * sizeof(double) + 4096));
-  double* out = ws_ptr<double>(ctx, o_out);
+  // the two sums land in the caller's device buffer when one is given
+  double* out = sums_dev ? sums_dev : ws_ptr<double>(ctx, o_out);
   double* P = ws_ptr<double>(ctx, o_P);
   double* Q = ws_ptr<double>(ctx, o_Q);
   double* part = ws_ptr<double>(ctx, o_part);
@@ -343,6 +344,7 @@ static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, i
     RPID_CHECK(residual_bf16(ctx, m, n, kParts * k, (const uint16_t*)A, lda, Pb, kParts * k, Qb,
                              kParts * k, part, out));
   }
+  if (sums_dev) return RPID_OK;
   double h[2];
   RPID_CHECK(read_doubles(ctx, out, h, 2));
   *rel_fro = (h[1] > 0.0) ? sqrt(h[0] / h[1]) : 0.0;
@@ -1245,9 +1247,10 @@ int rpid_cur(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, 
   }
 }
 
-int rpid_residual(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
-                  int64_t lda, int64_t k, const int64_t* J, const double* Z, int64_t ldz,
-                  const int64_t* I, const double* U, int64_t ldu, double* rel_fro) {
+static int residual_entry(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_t m,
+                          int64_t n, int64_t lda, int64_t k, const int64_t* J, const double* Z,
+                          int64_t ldz, const int64_t* I, const double* U, int64_t ldu,
+                          double* rel_fro, double* sums_dev) {
   if (!ctx) return -1;
   if (which != RPID_RESIDUAL_ID && which != RPID_RESIDUAL_CUR && which != RPID_RESIDUAL_ROW_ID) return -2;
   if (!A) return -3;
@@ -1262,19 +1265,33 @@ int rpid_residual(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_
   if (which != RPID_RESIDUAL_ID && !I) return -12;
   if (which == RPID_RESIDUAL_CUR && !U) return -13;
   if (which == RPID_RESIDUAL_CUR && ldu < k) return -14;
-  if (!rel_fro) return -15;
+  if (!rel_fro && !sums_dev) return -15;
   RPID_HIP_CHECK(hipSetDevice(ctx->device));
   switch (a_t) {
     case RPID_F64:
       return residual_impl<double>(ctx, which, (const double*)A, a_t, m, n, lda, k, J, Z, ldz, I,
-                                   U, ldu, rel_fro);
+                                   U, ldu, rel_fro, sums_dev);
     case RPID_F32:
       return residual_impl<float>(ctx, which, (const float*)A, a_t, m, n, lda, k, J, Z, ldz, I, U,
-                                  ldu, rel_fro);
+                                  ldu, rel_fro, sums_dev);
     default:
       return residual_impl<uint16_t>(ctx, which, (const uint16_t*)A, a_t, m, n, lda, k, J, Z, ldz,
-                                     I, U, ldu, rel_fro);
+                                     I, U, ldu, rel_fro, sums_dev);
   }
+}
+
+int rpid_residual(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                  int64_t lda, int64_t k, const int64_t* J, const double* Z, int64_t ldz,
+                  const int64_t* I, const double* U, int64_t ldu, double* rel_fro) {
+  if (!rel_fro) return -15;
+  return residual_entry(ctx, which, A, a_t, m, n, lda, k, J, Z, ldz, I, U, ldu, rel_fro, nullptr);
+}
+
+int rpid_residual_sums(rpid_ctx ctx, int which, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                       int64_t lda, int64_t k, const int64_t* J, const double* Z, int64_t ldz,
+                       const int64_t* I, const double* U, int64_t ldu, double* sums) {
+  if (!sums) return -15;
+  return residual_entry(ctx, which, A, a_t, m, n, lda, k, J, Z, ldz, I, U, ldu, nullptr, sums);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,6 +64,7 @@ _SIGS = {
         [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, _I, _i, ctypes.POINTER(ctypes.c_double)],
     ),
     "rpid_cur": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _P, _I, ctypes.POINTER(_I)]),
+    "rpid_residual_sums": (_i, [_P, _i, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P]),
     "rpid_residual": (
         _i,
         [_P, _i, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _P, _I, ctypes.POINTER(ctypes.c_double)],
@@ -425,6 +426,22 @@ def rpid_residual(ctx, which, A, k, J, Z=None, I=None, U=None) -> float:
     return out.value
 
 
+def rpid_residual_sums(ctx, which, A, k, J, Z=None, I=None, U=None) -> torch.Tensor:
+    """Device FP64 [||A - P Q||_F^2, ||A||_F^2] for the residual `which`, on
+    the context's stream without synchronising."""
+    pa, m, n, lda = colmajor(A)
+    sums = torch.empty(2, dtype=torch.float64, device=A.device)
+    s = lib().rpid_residual_sums(
+        ctx.handle, int(which), pa, dtype_code(A), m, n, lda, k, J.data_ptr() if J is not None else None,
+        Z.data_ptr() if Z is not None else None, Z.stride(1) if Z is not None else k,
+        I.data_ptr() if I is not None else None,
+        U.data_ptr() if U is not None else None, U.stride(1) if U is not None else k,
+        sums.data_ptr(),
+    )
+    _check("rpid_residual_sums", s)
+    return sums
+
+
 def rpid_mlp_features(ctx, diagU, L, k_eff):
     f = torch.empty(L, dtype=torch.float32, device=diagU.device)
     _check("rpid_mlp_features",
@@ -470,11 +487,14 @@ def rpid_mlp_loss(ctx, yhat, target, tau):
 def decompose_overlapped(ctx, ctx2, A, Omega, k, refine_steps=None):
     """Alg. 2 end to end with both residuals, the two branches that follow
     the column pivots run concurrently: Z and the ID residual on ctx2's
-    stream (from a worker thread; the library calls release the interpreter
-    lock), the CUR step and its residual on ctx's stream.  ctx2 needs its own
-    stream; the two contexts have separate workspaces, so the branches share
-    nothing but their read-only inputs.  The results are those of the
-    sequential order (the same kernels on the same inputs)."""
+    stream (enqueued from a worker thread; the library calls release the
+    interpreter lock), the CUR step and its residual on ctx's stream.  The
+    worker starts after the CUR step's first launches are on their way, so
+    the CUR step's cooperative LUPP launch finds the compute units free (the
+    order that measured fastest).  ctx2 needs its own stream; the two contexts
+    have separate workspaces, so the branches share nothing but their
+    read-only inputs.  The results are those of the sequential order (the
+    same kernels on the same inputs)."""
     import threading
 
     X = rpid_sketch(ctx, A, Omega)

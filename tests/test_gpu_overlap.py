@@ -40,3 +40,27 @@ def test_overlapped_equals_sequential(dt):
         ctx2.close()
         ctx.close()
     assert np.isfinite(rid) and np.isfinite(rcur)
+
+
+def test_residual_sums_match_residual():
+    """rpid_residual_sums leaves [||A - PQ||^2, ||A||^2] on the device; its
+    ratio's square root is bitwise rpid_residual's value."""
+    import math
+
+    from paper_2104_05877_amd import rpid as R
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    m, n, k, l = 1024, 768, 32, 40
+    A, Om = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 32)
+    Ad = inputs.torch_colmajor(A, torch.bfloat16, "cuda")
+    Od = inputs.torch_colmajor(Om, torch.bfloat16, "cuda")
+    ctx = R.Context(0)
+    try:
+        d = R.decompose(ctx, Ad, Od, k)
+        for which, kw in ((R.RESIDUAL_ID, dict(Z=d["Z"])), (R.RESIDUAL_CUR, dict(I=d["I"], U=d["U"]))):
+            r = R.rpid_residual(ctx, which, Ad, k, d["J"], **kw)
+            s0, s1 = R.rpid_residual_sums(ctx, which, Ad, k, d["J"], **kw).tolist()
+            assert math.sqrt(s0 / s1) == r
+    finally:
+        ctx.close()
