@@ -98,6 +98,25 @@ def test_lupp_f64_parity(R, ctx, l, n, k, seed):
     np.testing.assert_allclose(host(diag), f["diag"], rtol=0, atol=tol)
 
 
+def test_lupp_f64_largest_k(R, ctx):
+    """The largest k the boundary accepts (k = l = 1024; 2048 candidates):
+    FP64 pivots bit-exact, factors within the same tolerances."""
+    l = n_l = 1024
+    n, k = 2048, 1024
+    say("lupp_f64 largest k", l, n, k)
+    X = np.random.default_rng(9).standard_normal((l, n))
+    f = O.lupp_colwise(X, k, gaps=True)
+    assert f["gap"].min() > 1e-9 and n_l == k
+    J, Lf, Uf, diag, keff, st = R.rpid_select_columns(ctx, dev(X), k)
+    assert st == 0 and keff == k
+    assert np.array_equal(host(J).astype(np.int64), f["J"])
+    tol = 1e-11 * max(1.0, np.abs(f["U"]).max())
+    np.testing.assert_allclose(host(Lf), f["L"], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(host(Uf), f["U"], rtol=0, atol=tol)
+    with pytest.raises(R.RpidError):
+        R.rpid_select_columns(ctx, dev(np.ones((1100, 2048))), 1025)
+
+
 @pytest.mark.parametrize("l,n,k,seed", [(40, 2000, 40, 7), (272, 8192, 256, 8)])
 def test_lupp_f32_parity(R, ctx, l, n, k, seed):
     """FP32 LUPP on FP32-representable data; the oracle runs in FP64 on the
