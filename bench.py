@@ -441,7 +441,7 @@ def learned_report(torch, ctx):
     from the plain FP64 path), then reach the tolerance on LEARN_TEST held-out
     matrices two ways: the BF16-profile network with the plain path as
     fallback, and the plain FP64 path with rank doubling from 8.  Both answers
-    are judged by the FP64 residual; times are wall-clock per matrix."""
+    are evaluated by the FP64 residual; times are wall-clock per matrix."""
     import numpy as np
 
     from paper_2104_05877_amd import inputs, learned as Lr

@@ -6,7 +6,7 @@ profile |u_tt| of the FP32 LUPP of a BF16 sketch (the pivots of eq.
 (def_LUPP) computed by Alg. 2 step 3 over all l steps) and predicts log2 of
 the smallest rank k whose interpolative decomposition (Sec. 4) meets a
 relative Frobenius tolerance.  Labels come from the plain FP64 path on the
-GPU; the plain path with rank doubling is both the fallback and the judge.
+GPU; the plain path with rank doubling is both the fallback and the reference.
 
 Every arithmetic step runs in the library's kernels through the C-ABI
 (sketch, LUPP, features, forward, loss, backward, Adam, Z, residual); this
@@ -138,7 +138,7 @@ def attempt(ctx, A64, Om64, k):
     X = R.rpid_sketch(ctx, A64, Om64[:k])
     J, Lf, Uf, _, k_eff, st = R.rpid_select_columns(ctx, X, k)
     if st != 0:
-        # an exactly zero pivot: the sketch has rank k_eff; judge rank k_eff
+        # an exactly zero pivot: the sketch has rank k_eff; evaluate rank k_eff
         if k_eff < 1:
             return 1.0
         k = k_eff

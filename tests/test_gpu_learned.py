@@ -177,7 +177,7 @@ def _dataset(ctx, L, idx_range, l_feat):
 
 
 def test_learned_rank_gain(R, ctx, L):
-    """Train on 160 matrices of the stream, judge on 48 held out: every
+    """Train on 160 matrices of the stream, evaluate on 48 held out: every
     answer meets the tolerance (the plain path is the fallback), and the
     network needs fewer FP64 attempts than rank doubling from 4."""
     say("learned gain: building the stream")
