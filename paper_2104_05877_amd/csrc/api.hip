@@ -144,30 +144,30 @@ __global__ void sum_halves_kernel(int64_t k, int64_t n, const float* W2, double*
 }
 
 // ---------------------------------------------------------------------------
-// CUR: one Cholesky-QR pass over C (m x k) and R^T (n x k), both FP64:
-// Gram matrices, batched Cholesky (R upper), triangular inverses, and the
-// orthonormalised factors Qc = C Rc^{-1}, Qr = R^T Rr^{-1} as GEMMs.
-// F holds the two Cholesky factors (stride k*k), Wi their inverses.
-// ---------------------------------------------------------------------------
-static int chol_qr_pass(rpid_ctx ctx, int64_t m, int64_t n, int64_t k, const double* C,
-                        const double* Rt, double* Cq, double* Rq, double* F, double* Wi,
-                        int64_t* status_dev, size_t ws_tmp) {
+// CUR: Cholesky-QR passes over C (m x k) and R^T (n x k), both FP64.
+// One Cholesky-QR pass over one tall FP64 matrix X (rows x k): Gram,
+// Cholesky and the inverse of its factor (Wi = R^{-1}), Xq = X Wi.
+static int chol_qr_one(rpid_ctx ctx, int64_t rows, int64_t k, const double* X, double* Xq, double* F,
+                       double* Wi, int64_t* status_dev, size_t ws_tmp) {
   const int64_t kk = k * k;
-  RPID_CHECK(dgemm(ctx, true, false, k, k, m, 1.0, C, m, C, m, 0.0, F, k, ws_tmp));
-  RPID_CHECK(dgemm(ctx, true, false, k, k, n, 1.0, Rt, n, Rt, n, 0.0, F + kk, k, ws_tmp));
+  RPID_CHECK(dgemm(ctx, true, false, k, k, rows, 1.0, X, rows, X, rows, 0.0, F, k, ws_tmp));
   if (sweep_supported(k)) {
-    // Cholesky factors and their inverses in one launch (the factors
-    // themselves are not needed)
-    RPID_CHECK(chol_inverse_batched(ctx, 2, k, F, k, kk, Wi, k, kk, status_dev, ws_tmp));
+    RPID_CHECK(chol_inverse_batched(ctx, 1, k, F, k, kk, Wi, k, kk, status_dev, ws_tmp));
   } else {
-    RPID_CHECK(cholesky_batched(ctx, 2, k, F, k, kk, status_dev));
+    RPID_CHECK(cholesky_batched(ctx, 1, k, F, k, kk, status_dev));
     RPID_CHECK(tri_inverse(ctx, k, F, k, false, false, Wi, k, ws_tmp));
-    RPID_CHECK(tri_inverse(ctx, k, F + kk, k, false, false, Wi + kk, k, ws_tmp));
   }
-  RPID_CHECK(dgemm(ctx, false, false, m, k, k, 1.0, C, m, Wi, k, 0.0, Cq, m, ws_tmp));
-  RPID_CHECK(dgemm(ctx, false, false, n, k, k, 1.0, Rt, n, Wi + kk, k, 0.0, Rq, n, ws_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, rows, k, k, 1.0, X, rows, Wi, k, 0.0, Xq, rows, ws_tmp));
   return RPID_OK;
 }
+
+// Points the context's launches at another stream for a scope.
+struct StreamSwap {
+  rpid_ctx ctx;
+  hipStream_t saved;
+  StreamSwap(rpid_ctx c, hipStream_t s) : ctx(c), saved(c->stream) { c->stream = s; }
+  ~StreamSwap() { ctx->stream = saved; }
+};
 
 // ---------------------------------------------------------------------------
 template <typename TA>
@@ -181,8 +181,10 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   const size_t o_C32 = f64 ? 0 : cv.take<float>((size_t)m * k);
   const size_t o_Lc = cv.take<double>((size_t)m * k);  // LUPP multipliers (discarded)
   const size_t o_Uc = cv.take<double>((size_t)k * k);
+  const size_t o_Rg = cv.take<double>((size_t)k * n);
   const size_t o_Rt = cv.take<double>((size_t)n * k);
   const size_t o_C2 = cv.take<double>((size_t)m * k);
+  const size_t o_Qc = cv.take<double>((size_t)m * k);
   const size_t o_Rt2 = cv.take<double>((size_t)n * k);
   const size_t o_F = cv.take<double>((size_t)4 * k * k);
   const size_t o_Wi = cv.take<double>((size_t)4 * k * k);
@@ -191,76 +193,88 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   const size_t o_W2 = cv.take<float>((size_t)2 * k * n);
   const size_t o_Pt = cv.take<char>((size_t)m * 2 * k * 4);
   const size_t o_M = cv.take<double>((size_t)k * k);
-  const size_t o_tmp = cv.off;
-  const size_t tmp_bytes =
-      std::max(lupp_workspace_bytes(ctx, m, k, f64 ? 8 : 4),
-               std::max(sketch_workspace_bytes(ctx, m, n, 2 * k, 8),
-                        (size_t)64 * k * k * sizeof(double) + 4096));
-  RPID_CHECK(ensure_workspace(ctx, o_tmp + tmp_bytes));
+  // scratch of the main stream (small GEMM partials, triangular kernels) and
+  // of the side stream (the same, and the split-K partials of W's sketch)
+  const size_t small_tmp = (size_t)64 * k * k * sizeof(double) + 4096;
+  const size_t o_tmp = cv.take<char>(std::max(lupp_workspace_bytes(ctx, m, k, f64 ? 8 : 4), small_tmp));
+  const size_t o_tmp2 = cv.off;
+  RPID_CHECK(ensure_workspace(ctx, o_tmp2 + std::max(sketch_workspace_bytes(ctx, m, n, 2 * k, 8), small_tmp)));
   int64_t* status_dev = ws_ptr<int64_t>(ctx, o_status);
   double* C64 = ws_ptr<double>(ctx, o_C64);
   double* Rt = ws_ptr<double>(ctx, o_Rt);
   double* F = ws_ptr<double>(ctx, o_F);
+  double* Wi = ws_ptr<double>(ctx, o_Wi);
+  double* W = ws_ptr<double>(ctx, o_W);
+  double* Tc = ws_ptr<double>(ctx, o_T);
   const int64_t kk = k * k;
+  double* Tr = Tc + kk;
+  double* Y = Tc + 2 * kk;
 
-  // (S5) C = A(:, J); (S6) row-wise LUPP on C gives I
+  // (S5) C = A(:, J)
   RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(I), (size_t)k, 0ull));
   RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, C64, m));
-  // the LUPP status goes to slot 4 and is read with the Cholesky statuses at
-  // the end (one host synchronisation per call): after a zero pivot the rest
-  // runs on the zero-filled tail of I, which only reads valid rows of A
+  if (!f64) RPID_CHECK(gather_columns<TA, float>(ctx, m, k, A, lda, n, J, ws_ptr<float>(ctx, o_C32), m));
+
+  // Side stream: everything that needs C but not I -- Cholesky-QR2 of C
+  // (Q_C, the inverses of its two factors, Tc = their product) and
+  // W = Q_C^T A -- runs beside the row LUPP.  Only C (read) is shared; the
+  // side's regions and scratch are its own.
+  RPID_HIP_CHECK(hipEventRecord(ctx->ev_fork, ctx->stream));
+  RPID_HIP_CHECK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  {
+    StreamSwap on_side(ctx, ctx->side);
+    double* C2 = ws_ptr<double>(ctx, o_C2);
+    double* Qc = ws_ptr<double>(ctx, o_Qc);
+    RPID_CHECK(chol_qr_one(ctx, m, k, C64, C2, F, Wi, status_dev, o_tmp2));
+    RPID_CHECK(chol_qr_one(ctx, m, k, C2, Qc, F + 2 * kk, Wi + 2 * kk, status_dev + 2, o_tmp2));
+    RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi, k, Wi + 2 * kk, k, 0.0, Tc, k, o_tmp2));
+    // W = Q_C^T A (k x n), in the arithmetic of A's storage
+    if (a_t == RPID_F64) {
+      RPID_CHECK(sketch_f64(ctx, Qc, m, (const double*)A, lda, m, n, k, W, k, o_tmp2));
+    } else if (a_t == RPID_F32) {
+      float* Pt = ws_ptr<float>(ctx, o_Pt);
+      float* W32 = ws_ptr<float>(ctx, o_W2);
+      RPID_CHECK(convert_matrix<double, float>(ctx, m, k, Qc, m, Pt, m));
+      RPID_CHECK(sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, k, W32, k, o_tmp2));
+      RPID_CHECK(convert_matrix<float, double>(ctx, k, n, W32, k, W, k));
+    } else {
+      uint16_t* Pt = ws_ptr<uint16_t>(ctx, o_Pt);
+      float* W2 = ws_ptr<float>(ctx, o_W2);
+      RPID_CHECK(split_bf16(ctx, m, k, Qc, m, 2, Pt, m));
+      RPID_CHECK(sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, 2 * k, W2, 2 * k, o_tmp2));
+      hipLaunchKernelGGL(sum_halves_kernel, dim3(4096), dim3(256), 0, ctx->stream, k, n, W2, W);
+      RPID_HIP_CHECK(hipGetLastError());
+    }
+    RPID_HIP_CHECK(hipEventRecord(ctx->ev_join, ctx->stream));
+  }
+
+  // (S6) row-wise LUPP on C gives I.  Its status goes to slot 4 and is read
+  // with the Cholesky statuses at the end (one host synchronisation per
+  // call): after a zero pivot the rest runs on the zero-filled tail of I,
+  // which only reads valid rows of A.
   int64_t* lupp_status = status_dev + 4;
   if (f64) {
     RPID_CHECK(lupp_panel<double>(ctx, C64, 1, m, m, k, I, ws_ptr<double>(ctx, o_Lc), m,
                                   ws_ptr<double>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
   } else {
-    float* C32 = ws_ptr<float>(ctx, o_C32);
-    RPID_CHECK(gather_columns<TA, float>(ctx, m, k, A, lda, n, J, C32, m));
-    RPID_CHECK(lupp_panel<float>(ctx, C32, 1, m, m, k, I, ws_ptr<float>(ctx, o_Lc), m,
+    RPID_CHECK(lupp_panel<float>(ctx, ws_ptr<float>(ctx, o_C32), 1, m, m, k, I, ws_ptr<float>(ctx, o_Lc), m,
                                  ws_ptr<float>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
   }
 
-  // (S7) R^T = A(I, :)^T (n x k), orthonormal bases by Cholesky-QR2
-  RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, ws_ptr<double>(ctx, o_W), k));
-  RPID_CHECK(transpose_f64(ctx, k, n, ws_ptr<double>(ctx, o_W), k, Rt, n));
-  double* C2 = ws_ptr<double>(ctx, o_C2);
+  // (S7) R^T = A(I, :)^T (n x k), Cholesky-QR2 into Q_R (in Rt), Tr; then,
+  // with the side stream joined, M = W Q_R and U = Tc M Tr^T
+  // (U = R_C^{-1} (Q_C^T A Q_R) R_R^{-T}, R_C^{-1} = W1c W2c, R_R^{-1} = W1r W2r).
+  // A breakdown leaves garbage, never a fault, in what follows; the statuses
+  // are checked once at the end.
+  RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, ws_ptr<double>(ctx, o_Rg), k));
+  RPID_CHECK(transpose_f64(ctx, k, n, ws_ptr<double>(ctx, o_Rg), k, Rt, n));
   double* Rt2 = ws_ptr<double>(ctx, o_Rt2);
-  double* Wi = ws_ptr<double>(ctx, o_Wi);
-  // pass 1: C, R^T -> C2, Rt2 (factors R1c, R1r in F[0..2), inverses in Wi[0..2))
-  // (a breakdown in pass 1 leaves garbage, never a fault, in what follows; the
-  // four statuses are checked once at the end)
-  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C64, Rt, C2, Rt2, F, Wi, status_dev, o_tmp));
-  // pass 2: C2, Rt2 -> Q_C (into C64), Q_R (into Rt) (factors R2c, R2r, inverses)
-  RPID_CHECK(chol_qr_pass(ctx, m, n, k, C2, Rt2, C64, Rt, F + 2 * kk, Wi + 2 * kk, status_dev + 2,
-                          o_tmp));
-  // W = Q_C^T A (k x n), in the arithmetic of A's storage
-  double* W = ws_ptr<double>(ctx, o_W);
-  if (a_t == RPID_F64) {
-    RPID_CHECK(sketch_f64(ctx, C64, m, (const double*)A, lda, m, n, k, W, k, o_tmp));
-  } else if (a_t == RPID_F32) {
-    float* Pt = ws_ptr<float>(ctx, o_Pt);
-    float* W32 = ws_ptr<float>(ctx, o_W2);
-    RPID_CHECK(convert_matrix<double, float>(ctx, m, k, C64, m, Pt, m));
-    RPID_CHECK(sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, k, W32, k, o_tmp));
-    RPID_CHECK(convert_matrix<float, double>(ctx, k, n, W32, k, W, k));
-  } else {
-    uint16_t* Pt = ws_ptr<uint16_t>(ctx, o_Pt);
-    float* W2 = ws_ptr<float>(ctx, o_W2);
-    RPID_CHECK(split_bf16(ctx, m, k, C64, m, 2, Pt, m));
-    RPID_CHECK(sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, 2 * k, W2, 2 * k, o_tmp));
-    hipLaunchKernelGGL(sum_halves_kernel, dim3(4096), dim3(256), 0, ctx->stream, k, n, W2, W);
-    RPID_HIP_CHECK(hipGetLastError());
-  }
-  // M = W Q_R (k x k)
+  RPID_CHECK(chol_qr_one(ctx, n, k, Rt, Rt2, F + kk, Wi + kk, status_dev + 1, o_tmp));
+  RPID_CHECK(chol_qr_one(ctx, n, k, Rt2, Rt, F + 3 * kk, Wi + 3 * kk, status_dev + 3, o_tmp));
+  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi + kk, k, Wi + 3 * kk, k, 0.0, Tr, k, o_tmp));
+  RPID_HIP_CHECK(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
   double* M = ws_ptr<double>(ctx, o_M);
   RPID_CHECK(dgemm(ctx, false, false, k, k, n, 1.0, W, k, Rt, n, 0.0, M, k, o_tmp));
-  // U = R_C^{-1} M R_R^{-T} with R_C = R2c R1c, R_R = R2r R1r:
-  // U = (W1c W2c) M (W1r W2r)^T, W = inverses of the Cholesky factors
-  double* Tc = ws_ptr<double>(ctx, o_T);
-  double* Tr = Tc + kk;
-  double* Y = Tc + 2 * kk;
-  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi, k, Wi + 2 * kk, k, 0.0, Tc, k, o_tmp));
-  RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi + kk, k, Wi + 3 * kk, k, 0.0, Tr, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Tc, k, M, k, 0.0, Y, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, true, k, k, k, 1.0, Y, k, Tr, k, 0.0, U, ldu, o_tmp));
   RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 5 * sizeof(int64_t),
@@ -394,6 +408,12 @@ int rpid_create(rpid_ctx* out, int device, void* hip_stream) {
     delete c;
     return RPID_ERR_HIP;
   }
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    rpid_destroy(c);
+    return RPID_ERR_HIP;
+  }
   *out = c;
   return RPID_OK;
 }
@@ -414,6 +434,13 @@ int rpid_destroy(rpid_ctx ctx) {
     const hipError_t e3 = hipHostFree(ctx->host_status);
     if (e == hipSuccess) e = e3;
   }
+  if (ctx->side) {
+    const hipError_t e4 = hipStreamSynchronize(ctx->side);
+    const hipError_t e5 = hipStreamDestroy(ctx->side);
+    if (e == hipSuccess) e = e4 != hipSuccess ? e4 : e5;
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   delete ctx;
   return e == hipSuccess ? RPID_OK : RPID_ERR_HIP;
 }

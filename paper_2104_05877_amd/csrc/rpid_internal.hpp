@@ -23,6 +23,10 @@ struct rpid_ctx_s {
   void* uc = nullptr;
   size_t uc_bytes = 0;
   unsigned lupp_epoch = 0;  // tag of the LUPP exchange words of the latest launch
+  // A second stream (default priority) and two events, for work inside one
+  // call that can run beside the main stream's (fork and join by events).
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace rpid {
