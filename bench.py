@@ -207,9 +207,13 @@ def power_report(torch, R, ctx, A, Om, plain):
     I, U, keff_i, st_i = R.rpid_cur(ctx, A, K, J)
     rid = R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, J, Z=Z)
     rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, A, K, J, I=I, U=U)
+    # Rand-CPQR-1piter on the same power sketch (column-pivoted QR, its own Z)
+    Jq, Rq, _, _, stq = R.rpid_select_columns_cpqr(ctx, X, K)
+    rid_q = R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, Jq, Z=R.rpid_id_coeffs_cpqr(ctx, K, Jq, Rq))
     return {"sketch_power1_ms": ms, "sketch_ms": plain["per_call_ms"]["sketch"],
             "residual_id": rid, "residual_cur": rcur,
             "residual_id_plain": plain["rid"], "residual_cur_plain": plain["rcur"],
+            "residual_id_cpqr_1piter": rid_q,
             "status_columns": st, "status_rows": st_i}
 
 
