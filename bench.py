@@ -185,6 +185,44 @@ def sketch_loop(torch, R, ctx, A, Om, reps=20):
     return e0.elapsed_time(e1) / reps
 
 
+def sketch_shapes_report(torch, R, ctx, reps=10):
+    """The sketch call on the two larger sketch workloads, random operands
+    (timing does not depend on the values): A 16384 x 16384 BF16 with l = 544
+    (arithmetic intensity above the BF16 ridge, so the MFMA rate bounds it),
+    and the FP8 sketch of a 65536 x 4096 FP32 matrix with l = 400 (the call
+    includes the per-column E4M3 quantisation of A, a read of 4mn and a write
+    of mn bytes).  GPU time per call back to back; utilisation = 2lmn flops per
+    call over the dense MFMA peak of the operand type."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    out = {}
+    for name, (m, n, l, fp8) in {"bf16_16384x16384_l544": (16384, 16384, 544, False),
+                                 "fp8_65536x4096_l400": (65536, 4096, 400, True)}.items():
+        if fp8:
+            A = torch.randn((n, m), device="cuda", generator=g).abs_().T
+            Om = torch.randn((m, l), device="cuda", generator=g).T
+            call, peak = (lambda: R.rpid_sketch_fp8(ctx, A, Om)), 5.0e15
+        else:
+            A = torch.randn((n, m), device="cuda", generator=g).to(torch.bfloat16).T
+            Om = torch.randn((m, l), device="cuda", generator=g).to(torch.bfloat16).T
+            call, peak = (lambda: R.rpid_sketch(ctx, A, Om)), PEAK_MFMA["bf16"]
+        for _ in range(2):
+            call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            call()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms_per_call": ms, "tflops": 2.0 * l * m * n / (ms * 1e-3) / 1e12,
+                     "mfma_util": 2.0 * l * m * n / (ms * 1e-3) / peak}
+        del A, Om
+        torch.cuda.empty_cache()
+    return out
+
+
 def power_report(torch, R, ctx, A, Om, plain):
     """Rand-LUPP-1piter: the row sketch X = Omega A^T A (eq. def_power_iter,
     q = 1) in place of Omega A, same l, same Omega values.  GPU time per
@@ -619,6 +657,8 @@ def main():
         line["cpqr"] = cpqr_report(torch, R, ctx, *data[args.mode], main_r)
         log("sparse-sketch report")
         line["sparse"] = sparse_report(torch, R, ctx, *data[args.mode])
+        log("sketch on the larger sketch workloads")
+        line["sketch_shapes"] = sketch_shapes_report(torch, R, ctx)
     if not args.no_learned and not args.only_main:
         log("learned-rank report")
         line["learned_rank"] = learned_report(torch, ctx)

@@ -300,7 +300,9 @@ static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, i
   Carve cv;
   const size_t o_out = cv.take<double>(8);
   const size_t o_P = cv.take<double>((size_t)m * k);
-  const size_t o_Q = cv.take<double>((size_t)k * n);
+  // Q also holds C = A(:, J) (m x k) before the CUR form's product C U
+  const size_t q_elems = (size_t)k * (which == RPID_RESIDUAL_CUR ? std::max(m, n) : n);
+  const size_t o_Q = cv.take<double>(q_elems);
   const size_t o_Pb = bf ? cv.take<uint16_t>((size_t)m * kParts * k) : 0;
   const size_t o_Qb = bf ? cv.take<uint16_t>((size_t)kParts * k * n) : 0;
   const size_t o_Qs = bf ? cv.take<uint16_t>((size_t)kParts * k * n) : 0;
