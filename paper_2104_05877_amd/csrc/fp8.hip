@@ -57,25 +57,65 @@ __device__ __forceinline__ float block_max(float v, float* red) {
   return r;
 }
 
-// one workgroup per column: max |A(:, j)| -> ea[j], then the quantised column
-__global__ __launch_bounds__(256) void quantize_cols_kernel(const float* A, int64_t m, int64_t lda,
-                                                            uint8_t* Aq, int64_t ldq, int* ea) {
-  __shared__ float red[4];
+// one workgroup per column: max |A(:, j)| -> ea[j], then the quantised column.
+// 1024-thread workgroups keep at most two columns per CU in flight, so the
+// columns being worked on fit the Infinity Cache and the second read of a
+// column (to quantise it) is served from there rather than from HBM.
+constexpr int QC_NT = 1024;
+
+__global__ __launch_bounds__(QC_NT) void quantize_cols_kernel(const float* A, int64_t m, int64_t lda,
+                                                              uint8_t* Aq, int64_t ldq, int* ea) {
+  __shared__ float red[QC_NT / 64];
   const int64_t j = blockIdx.x;
+  const int64_t t = threadIdx.x;
   const float* col = A + j * lda;
+  // eight independent loads per thread in flight per round
   float mx = 0.0f;
   bool nonfinite = false;
-  for (int64_t i = threadIdx.x; i < m; i += 256) {
-    const float v = fabsf(col[i]);
-    nonfinite |= !isfinite(v);
-    mx = fmaxf(mx, v);
+  for (int64_t b = 0; b < m; b += 8 * QC_NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = b + t + QC_NT * u;
+      v[u] = i < m ? fabsf(col[i]) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      nonfinite |= !isfinite(v[u]);
+      mx = fmaxf(mx, v[u]);
+    }
   }
   mx = block_max(mx, red);
   const bool any_nf = __syncthreads_or(nonfinite);
   const int e = any_nf ? 0 : scale_exp(mx);
-  if (threadIdx.x == 0) ea[j] = e;
+  if (t == 0) ea[j] = e;
+  // four codes per thread and one 4-byte store (ldq is a multiple of 512 and
+  // the workspace regions are 256-byte aligned), bytes for the tail of m;
+  // sixteen loads per thread in flight per round (four groups of four)
   uint8_t* q = Aq + j * ldq;
-  for (int64_t i = threadIdx.x; i < m; i += 256) {
+  const int64_t m4 = m & ~(int64_t)3;
+  for (int64_t b = 0; b < m4; b += 16 * QC_NT) {
+    float v[4][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = b + 4 * QC_NT * g + 4 * t + u;
+        v[g][u] = i < m4 ? col[i] : 0.0f;
+      }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t i = b + 4 * QC_NT * g + 4 * t;
+      if (i < m4) {  // i is a multiple of 4, so i + 3 < m4 as well
+        uint32_t w = 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          w |= (e4m3_code(isfinite(v[g][u]) ? ldexpf(v[g][u], e) : NAN) & 0xffu) << (8 * u);
+        *reinterpret_cast<uint32_t*>(q + i) = w;
+      }
+    }
+  }
+  for (int64_t i = m4 + t; i < m; i += QC_NT) {
     const float v = col[i];
     q[i] = (uint8_t)e4m3_code(isfinite(v) ? ldexpf(v, e) : NAN);
   }
@@ -84,33 +124,45 @@ __global__ __launch_bounds__(256) void quantize_cols_kernel(const float* A, int6
 // partial maxima of |Omega| (l x m), one per workgroup
 __global__ __launch_bounds__(256) void omega_max_kernel(const float* Om, int64_t l, int64_t m,
                                                         int64_t ldo, float* part) {
+  // each wave takes two columns per round, its lanes along the rows, so up
+  // to sixteen loads per lane are in flight (no per-element index division)
   __shared__ float red[4];
   float mx = 0.0f;
-  const int64_t total = l * m;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const float v = fabsf(Om[(e % l) + (e / l) * ldo]);
-    mx = (v == v) ? fmaxf(mx, v) : INFINITY;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < m; i += 2 * stride) {
+    for (int64_t r0 = 0; r0 < l; r0 += 512) {
+      float v[2][8];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t ic = i + c * stride, r = r0 + lane + 64 * u;
+          v[c][u] = (ic < m && r < l) ? fabsf(Om[r + ic * ldo]) : 0.0f;
+        }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mx = (v[c][u] == v[c][u]) ? fmaxf(mx, v[c][u]) : INFINITY;
+    }
   }
   mx = block_max(mx, red);
   if (threadIdx.x == 0) part[blockIdx.x] = mx;
 }
 
 // eo from the partial maxima, then Pt_q = e4m3(Omega^T * 2^eo) (m x l, ldq)
-// through 32 x 32 LDS tiles; every workgroup reduces the partials itself
+// through 32 x 32 LDS tiles; every workgroup reduces the partials itself,
+// all its threads at once
 __global__ __launch_bounds__(256) void quantize_omega_t_kernel(const float* Om, int64_t l, int64_t m,
                                                                int64_t ldo, const float* part,
                                                                int nparts, uint8_t* Ptq,
                                                                int64_t ldq, int* eo_out) {
   __shared__ float tile[32][33];
-  __shared__ int s_e;
-  if (threadIdx.x == 0) {
-    float mx = 0.0f;
-    for (int i = 0; i < nparts; ++i) mx = fmaxf(mx, part[i]);
-    s_e = scale_exp(mx);
-    if (blockIdx.x == 0 && blockIdx.y == 0) *eo_out = s_e;
-  }
-  __syncthreads();
-  const int e = s_e;
+  __shared__ float red[4];
+  float pm = 0.0f;
+  for (int i = threadIdx.x; i < nparts; i += 256) pm = fmaxf(pm, part[i]);
+  const int e = scale_exp(block_max(pm, red));
+  if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) *eo_out = e;
   const int64_t r0 = (int64_t)blockIdx.y * 32, i0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int yy = ty; yy < 32; yy += 8) {
@@ -173,7 +225,7 @@ int sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, 
     RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Aq), (size_t)mq * n / 8, 0ull));
     RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Pq), (size_t)mq * l / 8, 0ull));
   }
-  hipLaunchKernelGGL(quantize_cols_kernel, dim3((unsigned)n), dim3(256), 0, ctx->stream, A, m, lda,
+  hipLaunchKernelGGL(quantize_cols_kernel, dim3((unsigned)n), dim3(QC_NT), 0, ctx->stream, A, m, lda,
                      Aq, mq, ea);
   RPID_HIP_CHECK(hipGetLastError());
   int parts = (int)std::min<int64_t>(OMAX_PARTS, (l * m + 255) / 256);
