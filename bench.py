@@ -62,6 +62,9 @@ def parse():
                     help="report the sequential step as the value (no concurrent Z / CUR branches)")
     ap.add_argument("--two-sided-only", action="store_true",
                     help="run only the Alg. 3 and Rand-CPQR reports on the main mode's input (for profiling)")
+    ap.add_argument("--sketch-shapes-only", action="store_true",
+                    help="run only the sketch report on the 16384^2 BF16 and 65536 x 4096 FP8 "
+                         "shapes (for profiling; no poly8192 input)")
     ap.add_argument("--input-cache", default=None,
                     help="folder: load the FP32 workload from it if stored there, else "
                          "generate it and store it (lets profiled runs skip the QR-based "
@@ -548,6 +551,12 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.sketch_shapes_only:
+        ctx = R.Context(0)
+        rep = sketch_shapes_report(torch, R, ctx)
+        ctx.close()
+        print(json.dumps({"sketch_shapes": rep}), flush=True)
+        return
     log("generating poly8192 inputs on the GPU")
     data = make_inputs(torch, args.seed, args.input_cache)
     calibration_copy(torch)
