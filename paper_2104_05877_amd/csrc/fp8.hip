@@ -150,19 +150,21 @@ __global__ __launch_bounds__(256) void omega_max_kernel(const float* Om, int64_t
   if (threadIdx.x == 0) part[blockIdx.x] = mx;
 }
 
-// eo from the partial maxima, then Pt_q = e4m3(Omega^T * 2^eo) (m x l, ldq)
-// through 32 x 32 LDS tiles; every workgroup reduces the partials itself,
-// all its threads at once
-__global__ __launch_bounds__(256) void quantize_omega_t_kernel(const float* Om, int64_t l, int64_t m,
-                                                               int64_t ldo, const float* part,
-                                                               int nparts, uint8_t* Ptq,
-                                                               int64_t ldq, int* eo_out) {
-  __shared__ float tile[32][33];
+// eo from the partial maxima (one workgroup)
+__global__ __launch_bounds__(256) void omega_scale_kernel(const float* part, int nparts, int* eo) {
   __shared__ float red[4];
   float pm = 0.0f;
   for (int i = threadIdx.x; i < nparts; i += 256) pm = fmaxf(pm, part[i]);
   const int e = scale_exp(block_max(pm, red));
-  if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0) *eo_out = e;
+  if (threadIdx.x == 0) *eo = e;
+}
+
+// Pt_q = e4m3(Omega^T * 2^eo) (m x l, ldq) through 32 x 32 LDS tiles
+__global__ __launch_bounds__(256) void quantize_omega_t_kernel(const float* Om, int64_t l, int64_t m,
+                                                               int64_t ldo, const int* eo,
+                                                               uint8_t* Ptq, int64_t ldq) {
+  __shared__ float tile[32][33];
+  const int e = *eo;
   const int64_t r0 = (int64_t)blockIdx.y * 32, i0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int yy = ty; yy < 32; yy += 8) {
@@ -191,7 +193,7 @@ __global__ void unscale_kernel(float* X, int64_t l, int64_t n, int64_t ldx, cons
   }
 }
 
-constexpr int OMAX_PARTS = 512;
+constexpr int OMAX_PARTS = 4096;
 
 }  // namespace
 
@@ -228,11 +230,14 @@ int sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, 
   hipLaunchKernelGGL(quantize_cols_kernel, dim3((unsigned)n), dim3(QC_NT), 0, ctx->stream, A, m, lda,
                      Aq, mq, ea);
   RPID_HIP_CHECK(hipGetLastError());
-  int parts = (int)std::min<int64_t>(OMAX_PARTS, (l * m + 255) / 256);
+  // at least eight columns of Omega per workgroup (two rounds of its four waves)
+  const int parts = (int)std::min<int64_t>(OMAX_PARTS, (m + 7) / 8);
   hipLaunchKernelGGL(omega_max_kernel, dim3(parts), dim3(256), 0, ctx->stream, Om, l, m, ldo, part);
   RPID_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(omega_scale_kernel, dim3(1), dim3(256), 0, ctx->stream, part, parts, eo);
+  RPID_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(quantize_omega_t_kernel, dim3((unsigned)((m + 31) / 32), (unsigned)((l + 31) / 32)),
-                     dim3(256), 0, ctx->stream, Om, l, m, ldo, part, parts, Pq, mq, eo);
+                     dim3(256), 0, ctx->stream, Om, l, m, ldo, eo, Pq, mq);
   RPID_HIP_CHECK(hipGetLastError());
   RPID_CHECK(sketch_e4m3(ctx, Pq, mq, Aq, mq, mq, n, l, X, ldx, o_gemm));
   int64_t blocks = (l * n + 255) / 256;
