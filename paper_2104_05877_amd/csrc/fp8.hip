@@ -58,10 +58,11 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 }
 
 // one workgroup per column: max |A(:, j)| -> ea[j], then the quantised column.
-// 1024-thread workgroups keep at most two columns per CU in flight, so the
-// columns being worked on fit the Infinity Cache and the second read of a
-// column (to quantise it) is served from there rather than from HBM.
-constexpr int QC_NT = 1024;
+// Columns of up to 4 QC_NT QC_G rows are held in registers (128 values per
+// thread, one workgroup per CU), so A is read once; longer columns take two
+// passes.
+constexpr int QC_NT = 512;
+constexpr int QC_G = 32;
 
 __global__ __launch_bounds__(QC_NT) void quantize_cols_kernel(const float* A, int64_t m, int64_t lda,
                                                               uint8_t* Aq, int64_t ldq, int* ea) {
@@ -69,7 +70,52 @@ __global__ __launch_bounds__(QC_NT) void quantize_cols_kernel(const float* A, in
   const int64_t j = blockIdx.x;
   const int64_t t = threadIdx.x;
   const float* col = A + j * lda;
-  // eight independent loads per thread in flight per round
+  if (m <= (int64_t)QC_G * 4 * QC_NT) {
+    // the whole column in registers (thread t holds elements 4 QC_NT g + 4 t + u),
+    // read once, every load in flight together
+    float v[QC_G][4];
+#pragma unroll
+    for (int g = 0; g < QC_G; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = 4 * QC_NT * g + 4 * t + u;
+        v[g][u] = i < m ? col[i] : 0.0f;
+      }
+    float cm = 0.0f;
+    bool cnf = false;
+#pragma unroll
+    for (int g = 0; g < QC_G; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float a = fabsf(v[g][u]);
+        cnf |= !isfinite(a);
+        cm = fmaxf(cm, a);
+      }
+    cm = block_max(cm, red);
+    const bool cnf_any = __syncthreads_or(cnf);
+    const int ce = cnf_any ? 0 : scale_exp(cm);
+    if (t == 0) ea[j] = ce;
+    uint8_t* cq = Aq + j * ldq;
+#pragma unroll
+    for (int g = 0; g < QC_G; ++g) {
+      const int64_t i = 4 * QC_NT * g + 4 * t;
+      uint32_t codes[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        codes[u] = e4m3_code(isfinite(v[g][u]) ? ldexpf(v[g][u], ce) : NAN) & 0xffu;
+      if (i + 3 < m) {  // ldq is a multiple of 512, so the 4-byte store is aligned
+        *reinterpret_cast<uint32_t*>(cq + i) =
+            codes[0] | (codes[1] << 8) | (codes[2] << 16) | (codes[3] << 24);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i + u < m) cq[i + u] = (uint8_t)codes[u];
+      }
+    }
+    return;
+  }
+  // longer columns: two passes over the column, eight independent loads per
+  // thread in flight per round
   float mx = 0.0f;
   bool nonfinite = false;
   for (int64_t b = 0; b < m; b += 8 * QC_NT) {
