@@ -57,6 +57,26 @@ __device__ __forceinline__ float block_max(float v, float* red) {
   return r;
 }
 
+// Four E4M3 codes packed little-endian into one word.  Where all four values
+// lie within +-448 the hardware conversion (two values per instruction,
+// round to nearest even; it agrees with e4m3_code on every float of that
+// range, checked on the device) forms them; otherwise (NaN, or a column whose
+// scale was left at 1 because it holds a non-finite entry) e4m3_code does.
+__device__ __forceinline__ uint32_t e4m3_pack4(float a, float b, float c, float d) {
+  if (fabsf(a) <= E4M3_MAX && fabsf(b) <= E4M3_MAX && fabsf(c) <= E4M3_MAX &&
+      fabsf(d) <= E4M3_MAX) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (uint32_t)w;
+  }
+  return (e4m3_code(a) & 0xffu) | ((e4m3_code(b) & 0xffu) << 8) | ((e4m3_code(c) & 0xffu) << 16) |
+         ((e4m3_code(d) & 0xffu) << 24);
+}
+
+__device__ __forceinline__ float scaled_or_nan(float v, int e) {
+  return isfinite(v) ? ldexpf(v, e) : NAN;
+}
+
 // one workgroup per column: max |A(:, j)| -> ea[j], then the quantised column.
 // Columns of up to 4 QC_NT QC_G rows are held in registers (128 values per
 // thread, one workgroup per CU), so A is read once; longer columns take two
@@ -99,17 +119,14 @@ __global__ __launch_bounds__(QC_NT) void quantize_cols_kernel(const float* A, in
 #pragma unroll
     for (int g = 0; g < QC_G; ++g) {
       const int64_t i = 4 * QC_NT * g + 4 * t;
-      uint32_t codes[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        codes[u] = e4m3_code(isfinite(v[g][u]) ? ldexpf(v[g][u], ce) : NAN) & 0xffu;
+      const uint32_t w = e4m3_pack4(scaled_or_nan(v[g][0], ce), scaled_or_nan(v[g][1], ce),
+                                    scaled_or_nan(v[g][2], ce), scaled_or_nan(v[g][3], ce));
       if (i + 3 < m) {  // ldq is a multiple of 512, so the 4-byte store is aligned
-        *reinterpret_cast<uint32_t*>(cq + i) =
-            codes[0] | (codes[1] << 8) | (codes[2] << 16) | (codes[3] << 24);
+        *reinterpret_cast<uint32_t*>(cq + i) = w;
       } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (i + u < m) cq[i + u] = (uint8_t)codes[u];
+          if (i + u < m) cq[i + u] = (uint8_t)(w >> (8 * u));
       }
     }
     return;
@@ -153,11 +170,9 @@ __global__ __launch_bounds__(QC_NT) void quantize_cols_kernel(const float* A, in
     for (int g = 0; g < 4; ++g) {
       const int64_t i = b + 4 * QC_NT * g + 4 * t;
       if (i < m4) {  // i is a multiple of 4, so i + 3 < m4 as well
-        uint32_t w = 0u;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          w |= (e4m3_code(isfinite(v[g][u]) ? ldexpf(v[g][u], e) : NAN) & 0xffu) << (8 * u);
-        *reinterpret_cast<uint32_t*>(q + i) = w;
+        *reinterpret_cast<uint32_t*>(q + i) =
+            e4m3_pack4(scaled_or_nan(v[g][0], e), scaled_or_nan(v[g][1], e),
+                       scaled_or_nan(v[g][2], e), scaled_or_nan(v[g][3], e));
       }
     }
   }
