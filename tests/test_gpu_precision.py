@@ -191,3 +191,40 @@ def test_bf16_residual_against_oracle(R, ctx, m, n, k, seed):
     say("cur", rcur, ro, bound)
     assert abs(rcur - ro) <= bound + 1e-12
 
+
+
+@pytest.mark.parametrize("m,l", [(302, 302), (70003, 300)])
+def test_fp8_codes_ties_and_subnormals_exact(R, ctx, m, l):
+    """The E4M3 codes themselves, exactly: Omega's rows are unit vectors
+    (scale 2^8, codes 256 exactly), so each row of X is one quantised row of A,
+    unscaled exactly.  Every column holds 448 (so its scale is 1), exact E4M3
+    values, midpoints of consecutive codes over the whole range including the
+    subnormals (ties: the even code must win) and arbitrary values.  m = 302
+    (all rows selected) leaves a ragged tail of two rows after the last group
+    of four; m = 70003 takes the two-pass quantisation of columns longer than
+    65536 rows (rows selected at random, plus the last ten)."""
+    n = 40
+    rng = np.random.default_rng(11)
+    table = O.e4m3_values()
+    k = rng.integers(0, table.size - 1, size=(m, n))
+    mids = (table[k] + table[k + 1]) / 2.0
+    even = np.where(k % 2 == 0, k, k + 1)
+    kind = rng.integers(0, 4, size=(m, n))  # 0, 1: midpoint, 2: exact value, 3: arbitrary
+    A = np.where(kind <= 1, mids, np.where(kind == 2, table[k], rng.uniform(0.0, 448.0, (m, n))))
+    A = A * np.where(rng.random((m, n)) < 0.5, -1.0, 1.0)
+    A[0, :] = 448.0
+    A = A.astype(np.float32).astype(np.float64)
+    if l == m:
+        rows = np.arange(m)
+    else:
+        rows = np.concatenate([np.sort(rng.choice(m - 10, l - 10, replace=False)), np.arange(m - 10, m)])
+    Om = np.zeros((l, m))
+    Om[np.arange(l), rows] = 1.0
+    say("fp8 codes", m, n, l)
+    X = host(R.rpid_sketch_fp8(ctx, inputs.torch_colmajor(A, torch.float32, "cuda"),
+                               inputs.torch_colmajor(Om, torch.float32, "cuda")))
+    expect = np.sign(A) * np.where(kind <= 1, table[even], np.where(kind == 2, table[k], np.nan))
+    sel = kind <= 2
+    sel[0, :] = False
+    assert np.array_equal(X[sel[rows]], expect[rows][sel[rows]])
+    assert np.array_equal(X, O.sketch_fp8(A, Om))
