@@ -233,11 +233,19 @@ __global__ __launch_bounds__(256) void quantize_omega_t_kernel(const float* Om, 
     tile[yy][tx] = (r < l && i < m) ? Om[r + i * ldo] : 0.0f;
   }
   __syncthreads();
-  for (int yy = ty; yy < 32; yy += 8) {
-    const int64_t i = i0 + tx, r = r0 + yy;
-    if (r < l && i < m) {
-      const float v = tile[tx][yy];
-      Ptq[i + r * ldq] = (uint8_t)e4m3_code(isfinite(v) ? ldexpf(v, e) : NAN);
+  // each thread: four consecutive codes of one row of Pt_q, one 4-byte store
+  // (ldq is a multiple of 512 and i0 of 32, so it is aligned)
+  const int rr = threadIdx.x >> 3, c4 = (threadIdx.x & 7) * 4;
+  const int64_t r = r0 + rr, i = i0 + c4;
+  if (r < l && i < m) {
+    const uint32_t w = e4m3_pack4(scaled_or_nan(tile[c4][rr], e), scaled_or_nan(tile[c4 + 1][rr], e),
+                                  scaled_or_nan(tile[c4 + 2][rr], e), scaled_or_nan(tile[c4 + 3][rr], e));
+    uint8_t* dst = Ptq + i + r * ldq;
+    if (i + 3 < m) {
+      *reinterpret_cast<uint32_t*>(dst) = w;
+    } else {
+      for (int u = 0; u < 4; ++u)
+        if (i + u < m) dst[u] = (uint8_t)(w >> (8 * u));
     }
   }
 }
