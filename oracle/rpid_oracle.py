@@ -13,6 +13,9 @@ randomized pivoting algorithms for CUR and interpolative decompositions":
                        eq. (def_power_iter) with q = 1: X = Omega A^T A.
 * lupp_colwise      -- column-wise LU with partial pivoting of Sec. 2.4,
                        eq. (def_LUPP), Alg. 2 step 3.
+* lupp_colwise_fma  -- the same steps in one fixed arithmetic (float64 or
+                       float32, correctly rounded divisions, fused Schur
+                       update), plain C in oracle/lupp_fma.c.
 * id_coeffs         -- ID coefficients from the pivoted sketch, Sec. 4:
                        C^+ A is estimated by X_1^+ X (X_1 = X(:, J_s)).
 * id_coeffs_ls      -- the same estimate by least squares over all l rows.
@@ -58,6 +61,10 @@ Readings of the paper taken here (the paper is silent or garbled on them):
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
 import scipy.linalg as sla
 
@@ -67,6 +74,7 @@ __all__ = [
     "e4m3_round",
     "fp8_scale_exp",
     "lupp_colwise",
+    "lupp_colwise_fma",
     "lupp_rowwise",
     "id_coeffs",
     "id_coeffs_ls",
@@ -247,6 +255,71 @@ def lupp_colwise(X, k, gaps=False):
     if gaps:
         out["gap"] = np.array(gap)
     return out
+
+
+# --------------------------------------------------------------------------
+# The same LUPP in one fixed arithmetic (oracle/lupp_fma.c): correctly
+# rounded divisions and a fused (single-rounding) Schur update, in float64 or
+# float32, so that a kernel doing the same operations can be compared bit for
+# bit.  Compiled on first use with the host C compiler.
+# --------------------------------------------------------------------------
+_FMA_LIB = None
+_HERE = os.path.dirname(os.path.abspath(__file__))
+FMA_SRC = os.path.join(_HERE, "lupp_fma.c")
+FMA_LIB = os.path.join(_HERE, "liblupp_fma.so")
+
+
+def build_fma_lib(force=False):
+    """Compile oracle/lupp_fma.c into oracle/liblupp_fma.so (contraction off:
+    the only fused operations are the explicit fma calls)."""
+    if force or not os.path.exists(FMA_LIB) or os.path.getmtime(FMA_LIB) < os.path.getmtime(FMA_SRC):
+        cc = os.environ.get("CC", "gcc")
+        tmp = FMA_LIB + ".tmp%d" % os.getpid()
+        subprocess.run([cc, "-O2", "-ffp-contract=off", "-fPIC", "-shared", FMA_SRC, "-o", tmp, "-lm"],
+                       check=True, capture_output=True)
+        os.replace(tmp, FMA_LIB)
+    return FMA_LIB
+
+
+def _fma_lib():
+    global _FMA_LIB
+    if _FMA_LIB is None:
+        lib = ctypes.CDLL(build_fma_lib())
+        P = ctypes.c_void_p
+        for name in ("lupp_fma_f64", "lupp_fma_f32"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P, P]
+        _FMA_LIB = lib
+    return _FMA_LIB
+
+
+def lupp_colwise_fma(X, k, dtype=np.float64):
+    """k steps of column-wise LUPP on X (l x n) as lupp_colwise, computed in
+    `dtype` (float64 or float32) with m = S(i, t) / S(p, t) rounded once and
+    the update S(i, c) = fma(-m, U(t, c), S(i, c)) rounded once.  X must be
+    exactly representable in `dtype`.  Same return keys as lupp_colwise
+    (L, U, diag in `dtype`)."""
+    dtype = np.dtype(dtype)
+    X = np.asarray(X)
+    l, n = X.shape
+    if not (1 <= k <= min(l, n)):
+        raise ValueError("need 1 <= k <= min(l, n)")
+    panel = np.ascontiguousarray(X[:k, :].T, dtype=dtype)
+    if not np.array_equal(panel.astype(np.float64), np.asarray(X[:k, :].T, dtype=np.float64), equal_nan=True):
+        raise ValueError("X is not exactly representable in %s" % dtype)
+    J = np.zeros(k, dtype=np.int64)
+    L = np.zeros((n, k), dtype=dtype)
+    U = np.zeros((k, k), dtype=dtype)
+    diag = np.zeros(k, dtype=dtype)
+    fn = _fma_lib().lupp_fma_f64 if dtype == np.float64 else _fma_lib().lupp_fma_f32
+    st = fn(n, k, panel.ctypes.data, J.ctypes.data, L.ctypes.data, U.ctypes.data, diag.ctypes.data)
+    if st == -1:
+        raise NonFiniteInput("non-finite entry in the sketch")
+    if st < -1:
+        raise MemoryError("lupp_fma")
+    k_eff = k if st == 0 else st - 1
+    return dict(J=J[:k_eff], L=L, U=U, diag=diag[:k_eff], k_eff=k_eff, status=st)
 
 
 def lupp_rowwise(C, k, gaps=False):

@@ -461,6 +461,33 @@ ALL_PINS += [pin_two_sided_bruteforce, pin_row_id_structure, pin_two_sided_exact
              pin_cur_sketch_inverse, pin_two_sided_bounds]
 
 
+def pin_rangefinder_closed_form(O, seed=59, m=40, n=30, k=6):
+    """The rangefinder error of Sec. 2.3 in closed form: for A = U diag(s) V^T
+    and a sketch whose first k rows span the right singular vectors V(:, S)
+    for an index set S, ||A - A X_k^+ X_k|| / ||A|| is the norm of the
+    singular values outside S over the norm of all of them (Frobenius:
+    root of the sum of squares; spectral: the largest left over over s_1).
+    Checked for the leading k vectors (the Eckart-Young optimum) and for a
+    set in the middle of the spectrum, so a value too large or too small
+    fails.  Rows of X past k are random and must not enter."""
+    rng = np.random.default_rng(seed)
+    s = np.linspace(3.0, 0.1, n)
+    U = inputs.haar(rng, m, n)
+    V = inputs.haar(rng, n, n)
+    A = (U * s) @ V.T
+    for S in (np.arange(k), np.arange(10, 10 + k)):
+        G = rng.standard_normal((k, k))
+        X = np.vstack([G @ V[:, S].T, rng.standard_normal((3, n))])
+        out = np.setdiff1d(np.arange(n), S)
+        ref_f = np.sqrt(np.sum(s[out] ** 2) / np.sum(s**2))
+        ref_2 = s[out].max() / s[0]
+        assert abs(O.rangefinder_error(A, X, k) - ref_f) <= 1e-12, S
+        assert abs(O.rangefinder_error(A, X, k, ord=2) - ref_2) <= 1e-12, S
+
+
+ALL_PINS += [pin_rangefinder_closed_form]
+
+
 def pin_cpqr_lapack(O, seed=50, l=12, n=40, k=9):
     """The CPQR pivots are LAPACK geqp3's (scipy, an independent
     implementation with the same greedy rule) on a tie-free sketch, and the

@@ -86,6 +86,10 @@ MUTANTS = {
     "SRTT permutation applied inverted": ("P[np.arange(m), np.asarray(perm)] = 1.0", "P[np.asarray(perm), np.arange(m)] = 1.0"),
     "least-squares Z over the first k rows only": ("    Z = np.linalg.lstsq(X[:, J], X, rcond=None)[0]",
                                                     "    Z = np.linalg.lstsq(X[:k][:, J], X[:k], rcond=None)[0]"),
+    "rangefinder projected on the row space of all l rows": ("    q, _ = np.linalg.qr(_f64(X)[:k, :].T)",
+                                                              "    q, _ = np.linalg.qr(_f64(X).T)"),
+    "rangefinder error of the projection instead of the remainder": (
+        "    E = A - (A @ q) @ q.T", "    E = (A @ q) @ q.T"),
     "row ID residual with C instead of R": ('out["rowid"] = nrm(A - _f64(W) @ R) / na',
                                             'out["rowid"] = nrm(A - _f64(W) @ R[:, ::-1]) / na'),
 }
@@ -98,6 +102,7 @@ def test_oracle_mutants_are_caught(name):
     src = open(O.__file__).read()
     assert src.count(old) == 1, name
     mod = types.ModuleType("oracle_mutant")
+    mod.__file__ = O.__file__
     exec(compile(src.replace(old, new), "oracle_mutant", "exec"), mod.__dict__)
     caught = []
     for pin in P.ALL_PINS:
