@@ -169,6 +169,22 @@ struct StreamSwap {
   ~StreamSwap() { ctx->stream = saved; }
 };
 
+// After work has been forked onto the side stream, every way out of the call
+// joins it back: on an early error return the main stream is made to wait for
+// everything enqueued on the side so far, so the next call on the context
+// cannot reuse workspace regions the side stream is still writing.
+struct SideJoin {
+  rpid_ctx ctx;
+  bool joined = false;
+  explicit SideJoin(rpid_ctx c) : ctx(c) {}
+  ~SideJoin() {
+    if (joined) return;
+    if (hipEventRecord(ctx->ev_join, ctx->side) != hipSuccess ||
+        hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
+      (void)hipStreamSynchronize(ctx->side);
+  }
+};
+
 // ---------------------------------------------------------------------------
 template <typename TA>
 static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
@@ -221,6 +237,7 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   // side's regions and scratch are its own.
   RPID_HIP_CHECK(hipEventRecord(ctx->ev_fork, ctx->stream));
   RPID_HIP_CHECK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  SideJoin side_join(ctx);
   {
     StreamSwap on_side(ctx, ctx->side);
     double* C2 = ws_ptr<double>(ctx, o_C2);
@@ -273,6 +290,7 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   RPID_CHECK(chol_qr_one(ctx, n, k, Rt2, Rt, F + 3 * kk, Wi + 3 * kk, status_dev + 3, o_tmp));
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi + kk, k, Wi + 3 * kk, k, 0.0, Tr, k, o_tmp));
   RPID_HIP_CHECK(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+  side_join.joined = true;
   double* M = ws_ptr<double>(ctx, o_M);
   RPID_CHECK(dgemm(ctx, false, false, k, k, n, 1.0, W, k, Rt, n, 0.0, M, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Tc, k, M, k, 0.0, Y, k, o_tmp));
@@ -423,11 +441,13 @@ int rpid_create(rpid_ctx* out, int device, void* hip_stream) {
 int rpid_destroy(rpid_ctx ctx) {
   if (!ctx) return -1;
   // every release is attempted; the first failure is reported.  The uncached
-  // exchange buffer stays allocated until the process ends (device memory of
-  // that kind is never freed once a kernel has read it).
+  // exchange buffer goes back to the device's pool and stays allocated until
+  // the process ends (device memory of that kind is never freed once a kernel
+  // has read it).
   hipError_t e = hipSetDevice(ctx->device);
   const hipError_t e1 = hipStreamSynchronize(ctx->stream);
   if (e == hipSuccess) e = e1;
+  if (e1 == hipSuccess) release_exchange_buffer(ctx);
   if (ctx->ws) {
     const hipError_t e2 = hipFree(ctx->ws);
     if (e == hipSuccess) e = e2;

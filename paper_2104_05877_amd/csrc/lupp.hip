@@ -28,6 +28,10 @@
 //    tagged halves).  Slots alternate between two buffers by step parity, so
 //    a slot is rewritten only after every workgroup has read it.
 //  One device-wide exchange per pivot; no second kernel launch per step.
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "rpid_internal.hpp"
 
 namespace rpid {
@@ -511,18 +515,59 @@ static int dispatch_R(rpid_ctx ctx, LuppArgs<T> a, int R, int G, int nt) {
   }
 }
 
-// The context's uncached exchange buffer, grown to `bytes` if needed (the
-// old one is left allocated on purpose), and a fresh launch epoch for the
-// tags; the buffer is cleared when it is new or the epoch wraps.
+// Uncached exchange buffers are never freed once a kernel has read them, so
+// they are pooled per device for the life of the process: a context takes one
+// at its first pivoting call and hands it back in rpid_destroy, so contexts
+// created in a loop reuse the same few buffers.  Each buffer carries its
+// launch epoch with it (the tag of the words its latest launch wrote), so a
+// launch on a recycled buffer never takes a stale word for a fresh one.
+namespace {
+struct UcBuffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+  unsigned epoch = 0;
+};
+std::mutex g_uc_mu;
+std::vector<std::pair<int, UcBuffer>> g_uc_pool;  // (device, buffer), free buffers
+}  // namespace
+
+void release_exchange_buffer(rpid_ctx ctx) {
+  if (!ctx->uc) return;
+  std::lock_guard<std::mutex> lk(g_uc_mu);
+  g_uc_pool.push_back({ctx->device, UcBuffer{ctx->uc, ctx->uc_bytes, ctx->lupp_epoch}});
+  ctx->uc = nullptr;
+  ctx->uc_bytes = 0;
+  ctx->lupp_epoch = 0;
+}
+
+// The context's uncached exchange buffer, at least `bytes` long, and a fresh
+// launch epoch for the tags; a buffer is cleared when it is new or its epoch
+// wraps.  A buffer that is too small goes back to the pool (still allocated).
 static int exchange_buffer(rpid_ctx ctx, size_t bytes, char** base, unsigned* epoch) {
   bool fresh = false;
   if (bytes > ctx->uc_bytes) {
-    size_t want = bytes < ((size_t)4 << 20) ? ((size_t)4 << 20) : bytes;
-    void* p = nullptr;
-    if (hipExtMallocWithFlags(&p, want, hipDeviceMallocUncached) != hipSuccess) return RPID_ERR_NOMEM;
-    ctx->uc = p;
-    ctx->uc_bytes = want;
-    fresh = true;
+    release_exchange_buffer(ctx);
+    {
+      std::lock_guard<std::mutex> lk(g_uc_mu);
+      for (size_t i = 0; i < g_uc_pool.size(); ++i) {
+        if (g_uc_pool[i].first == ctx->device && g_uc_pool[i].second.bytes >= bytes) {
+          ctx->uc = g_uc_pool[i].second.p;
+          ctx->uc_bytes = g_uc_pool[i].second.bytes;
+          ctx->lupp_epoch = g_uc_pool[i].second.epoch;
+          g_uc_pool.erase(g_uc_pool.begin() + i);
+          break;
+        }
+      }
+    }
+    if (!ctx->uc) {
+      size_t want = bytes < ((size_t)4 << 20) ? ((size_t)4 << 20) : bytes;
+      void* p = nullptr;
+      if (hipExtMallocWithFlags(&p, want, hipDeviceMallocUncached) != hipSuccess) return RPID_ERR_NOMEM;
+      ctx->uc = p;
+      ctx->uc_bytes = want;
+      ctx->lupp_epoch = 0;
+      fresh = true;
+    }
   }
   // launch epoch (21 bits) tags every exchanged word; tag 0 never matches
   if (++ctx->lupp_epoch >= (1u << 21)) {
@@ -574,7 +619,11 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
       G64 = G2;
     }
   }
-  if (G64 > 4096) return RPID_ERR_UNSUPPORTED;
+  // One workgroup per compute unit at most.  A grid of two workgroups per CU
+  // once ran into the spin limit of the exchange (the 384 x 65536 FP32 panel,
+  // before it moved to two threads per column) and the cause is not known, so
+  // such grids are refused rather than launched.
+  if (G64 > ctx->num_cu) return RPID_ERR_UNSUPPORTED;
   const int G = (int)G64;
   const int xstride = kpad;  // words per published row
 

@@ -17,9 +17,9 @@ struct rpid_ctx_s {
   size_t ws_bytes = 0;
   // Pinned host word for status read-back.
   int64_t* host_status = nullptr;
-  // Uncached device memory for the cross-workgroup exchange of the LUPP
-  // kernel.  Once a kernel has read it, it stays allocated until the process
-  // ends (a grown buffer replaces, but does not free, the previous one).
+  // Uncached device memory for the cross-workgroup exchange of the pivoting
+  // kernels, taken from a per-device pool and handed back by rpid_destroy.
+  // Once a kernel has read it, it stays allocated until the process ends.
   void* uc = nullptr;
   size_t uc_bytes = 0;
   unsigned lupp_epoch = 0;  // tag of the LUPP exchange words of the latest launch
@@ -115,6 +115,9 @@ int lupp_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, i
 template <typename T>
 int cpqr_panel(rpid_ctx ctx, const T* base, int64_t rs, int64_t cs, int64_t n, int64_t l, int64_t k,
                int64_t* J, T* Rf, int64_t ldr, T* diag, int64_t* status_dev);
+// Hand the context's uncached exchange buffer back to the per-device pool
+// (rpid_destroy); the buffer itself stays allocated.
+void release_exchange_buffer(rpid_ctx ctx);
 // Workspace bytes lupp_panel needs for an n x k panel.
 size_t lupp_workspace_bytes(rpid_ctx ctx, int64_t n, int64_t k, int elem_bytes);
 
