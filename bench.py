@@ -9,21 +9,27 @@ One step = one pass of the whole path over the resident inputs:
   sketch X = Omega A  ->  column LUPP on X (J, factors)  ->  Z (+1 FP64
   refinement in the FP32/BF16 modes)  ->  CUR (LUPP on C -> I, stable U)
   ->  ID and CUR residuals.
-Modes: bf16 (A and Omega stored BF16; BF16 MFMA sketch, FP32 LUPP, FP64
-Z/U), f32 (FP32 storage and arithmetic for sketch/LUPP), f64 (the FP32
-values of A promoted to FP64; FP64 everywhere).
+Modes: f64 (the FP32 values of A promoted to FP64; FP64 everywhere, the
+paper's arithmetic), f32 (FP32 storage and arithmetic for sketch/LUPP), bf16
+(A and Omega stored BF16; BF16 MFMA sketch, FP32 LUPP, FP64 Z/U).
 
 Prints one JSON line.  `value` is decompositions per second of the main
-mode (default bf16) with the inputs already in HBM.  `roofline` describes
-the kernel that takes the most time per step; `cpu_baseline` times the FP64
-numpy oracle on the host cores on one decomposition of the same workload.
+mode (default f64) with the inputs already in HBM, back-to-back steps (the
+256 MB last-level cache warm); `cold` repeats the step with a 512 MiB
+buffer written between steps.  `roofline` describes the call that takes the
+most time per step; `cpu_baseline` times the FP64 numpy oracle on the host
+cores on one decomposition of the same workload (all threads, and one
+thread); `parity` compares every mode's outputs with the FP64 oracle on the
+same stored values; `configs` runs the two precision forms at their own
+sizes (16384^2 BF16, k = 512; 65536 x 4096 with the FP8 sketch, k = 384).
 
-Before the timed region the script runs one plain device-to-device copy of
-CALIB_MIB MiB (a torch copy kernel that reads and writes exactly that many
-bytes); hardware byte counters taken over this same command are scaled by
-what they read for that copy.  `roofline.traffic` is filled from the
-counter summary committed under profiles/ only while the LUPP source file
-still has the hash recorded there, else it is null.
+Before the timed region the script runs plain device-to-device copies of
+CALIB_MIB MiB (an elementwise kernel that reads and writes exactly that many
+bytes), timed with events: the measured HBM ceiling.  Hardware byte
+counters taken over this same command are scaled by what they read for that
+copy.  `roofline.traffic` is filled from the counter summary committed under
+profiles/ only while the LUPP source file still has the hash recorded there,
+else it is null.
 """
 from __future__ import annotations
 
@@ -52,7 +58,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--mode", default="f64", choices=["bf16", "f32", "f64"],
+                    help="main mode: its step is `value` (f64 is the paper's arithmetic)")
+    ap.add_argument("--reports-mode", default="bf16", choices=["bf16", "f32", "f64"],
+                    help="storage of the input the reports of the added rows run on")
+    ap.add_argument("--cold-steps", type=int, default=10,
+                    help="steps of the main mode with the last-level cache flushed between steps")
+    ap.add_argument("--no-parity", action="store_true", help="skip the oracle comparison of every mode")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the precision forms at their own sizes")
     ap.add_argument("--other-steps", type=int, default=8, help="timed steps of the other two modes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
@@ -89,11 +103,7 @@ def make_inputs(torch, seed, cache=None):
         a32 = d["a_t"].cuda().T
         om32 = d["om_t"].cuda().T
     else:
-        s = inputs.poly_spectrum(N, 2.0)
-        a64 = inputs.torch_spectral(M, N, s, seed, "cuda")
-        a32 = a64.T.contiguous().float().T  # FP32 storage of the workload
-        del a64
-        om32 = inputs.torch_gaussian(L, M, seed + 7, "cuda").T.contiguous().float().T
+        a32, om32 = inputs.torch_poly8192(seed, "cuda", M, N, L)
         if path:
             os.makedirs(cache, exist_ok=True)
             torch.save({"a_t": a32.T.cpu(), "om_t": om32.T.cpu()}, path)
@@ -127,7 +137,7 @@ def run_mode(torch, R, ctx, A, Om, steps, warmup):
         ev[5].record(stream)
         rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, A, K, J, I=I, U=U)
         ev[6].record(stream)
-        return rid, rcur, st_i, J, I
+        return rid, rcur, st_i, J, I, X, Z, U, Lf, Uf
 
     def mk():
         return [torch.cuda.Event(enable_timing=True) for _ in range(7)]
@@ -148,11 +158,13 @@ def run_mode(torch, R, ctx, A, Om, steps, warmup):
             per[n] += ev[j].elapsed_time(ev[j + 1]) / steps  # ms
         step_ms.append(ev[0].elapsed_time(ev[6]))
         decomp_ms.append(ev[0].elapsed_time(ev[4]))
-    rid, rcur, st_i, J, I = out
+    rid, rcur, st_i, J, I, X, Z, U, Lf, Uf = out
     import numpy as np
 
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, per_call_ms=per, rid=rid, rcur=rcur,
                 status_cur=st_i, J=J.cpu().numpy(), I=I.cpu().numpy(),
+                X=X.double().cpu().numpy(), Z=Z.cpu().numpy(), U=U.cpu().numpy(),
+                Lf=Lf.double().cpu().numpy(), Uf=Uf.double().cpu().numpy(),
                 step_ms_p10_p50_p90=[float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
                 decomp_ms_p10_p50_p90=[float(np.percentile(decomp_ms, q)) for q in (10, 50, 90)])
 
@@ -385,17 +397,54 @@ def sparse_report(torch, R, ctx, A, Om):
             "csc_gaussian_gflops": 2.0 * len(va) * L / (ms_csc * 1e-3) / 1e9}
 
 
-def calibration_copy(torch):
-    """One elementwise kernel that reads CALIB_MIB MiB and writes CALIB_MIB MiB
+def calibration_copy(torch, reps=5):
+    """Elementwise kernels that read CALIB_MIB MiB and write CALIB_MIB MiB
     (a negating copy: a plain same-dtype copy would go to the DMA engines),
-    outside any timed region."""
+    outside any timed region.  Returns the best rate over `reps` launches in
+    bytes per second (read + write), the measured HBM ceiling (2 x 512 MiB
+    does not fit the 256 MB last-level cache)."""
     n = CALIB_MIB * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    torch.neg(src, out=dst)
-    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.neg(src, out=dst)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
     del src, dst
+    return 2.0 * CALIB_MIB * (1 << 20) / (best * 1e-3)
+
+
+def cold_steps(torch, R, ctx, A, Om, steps):
+    """The sequential step with the last-level cache flushed before each
+    step: a 512 MiB buffer is written between steps, outside the events
+    that bracket the step.  Per-step times (ms)."""
+    import numpy as np
+
+    refine = 0 if A.dtype == torch.float64 else 1
+    flush = torch.empty(CALIB_MIB * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    out = []
+    for i in range(steps + 1):
+        flush.fill_(float(i))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        X = R.rpid_sketch(ctx, A, Om)
+        J, Lf, Uf, _, _, _ = R.rpid_select_columns(ctx, X, K, sync=False)
+        Z, _ = R.rpid_id_coeffs(ctx, X, K, J, Lf, Uf, refine_steps=refine)
+        I, U, _, _ = R.rpid_cur(ctx, A, K, J)
+        R.rpid_residual(ctx, R.RESIDUAL_ID, A, K, J, Z=Z)
+        R.rpid_residual(ctx, R.RESIDUAL_CUR, A, K, J, I=I, U=U)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        if i > 0:
+            out.append(e0.elapsed_time(e1))
+    del flush
+    return [float(np.percentile(out, q)) for q in (10, 50, 90)]
 
 
 def _counter_rows(folder):
@@ -456,22 +505,146 @@ def recorded_traffic():
     return rec
 
 
-def cpu_baseline(torch, A, Om):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(torch, A, Om, threads_one=True):
     """The FP64 oracle, untuned, on the host: one decomposition (sketch, LUPP,
-    Z, CUR) plus its ID and CUR residuals on the same stored values."""
+    Z, CUR) plus its ID and CUR residuals on the same stored values, with
+    every BLAS thread and again with one thread.  GFLOP/s count the dominant
+    terms 2mn(l + 3k): the sketch, W = Q_C^T A and the two residual
+    products."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import oracle.rpid_oracle as O
 
     a = np.asfortranarray(A.double().cpu().numpy())
     om = np.asfortranarray(Om.double().cpu().numpy())
-    t0 = time.perf_counter()
-    d = O.decompose(a, om, K)
-    r = O.residuals(a, d["J"], Z=d["Z"], I=d["I"], U=d["U"], only=("id", "cur"))
-    t = time.perf_counter() - t0
+
+    def one():
+        t0 = time.perf_counter()
+        d = O.decompose(a, om, K, gaps=True)
+        r = O.residuals(a, d["J"], Z=d["Z"], I=d["I"], U=d["U"], only=("id", "cur"))
+        return time.perf_counter() - t0, d, r
+
+    t, d, r = one()
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    return dict(seconds=t, threads=threads, rid=r["id"], rcur=r["cur"], J=d["J"], I=d["I"])
+    t1 = None
+    if threads_one:
+        with threadpool_limits(1):
+            t1, _, _ = one()
+    flops = 2.0 * M * N * (L + 3 * K)
+    return dict(seconds=t, seconds_1thread=t1, threads=threads, gflops=flops / t / 1e9,
+                gflops_1thread=(flops / t1 / 1e9) if t1 else None, rid=r["id"], rcur=r["cur"],
+                oracle=d, nproc=os.cpu_count(), cpu_model=_cpu_model())
+
+
+def _rel(a, b):
+    import numpy as np
+
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def parity_report(res, o, name):
+    """A mode's last step against the FP64 oracle on the same stored values:
+    pivot prefix, overlap, equality; errors of X, Z, U; residual ratios; and
+    the column LUPP on the kernel's own X against the fixed-arithmetic
+    oracle in the kernel's precision (bit for bit: pivots, L', U')."""
+    import numpy as np
+
+    import oracle.rpid_oracle as O
+
+    J, I = res["J"].astype(np.int64), res["I"].astype(np.int64)
+    same_j = J == o["J"]
+    pj = int(np.argmin(same_j)) if not same_j.all() else K
+    same_i = I == o["I"] if len(o.get("I", [])) == K else np.zeros(K, bool)
+    pi = int(np.argmin(same_i)) if not same_i.all() else K
+    dt = np.float64 if name == "f64" else np.float32
+    f = O.lupp_colwise_fma(res["X"], K, dt)
+    out = {"J_equal": bool(pj == K), "I_equal": bool(pi == K), "J_prefix": pj, "I_prefix": pi,
+           "J_overlap": len(np.intersect1d(J, o["J"])) / K, "I_overlap": len(np.intersect1d(I, o["I"])) / K,
+           "X_rel_err": _rel(res["X"], o["X"]),
+           "lupp_bitexact_vs_fixed_arithmetic_oracle": bool(
+               np.array_equal(J, f["J"]) and np.array_equal(res["Lf"], f["L"].astype(np.float64))
+               and np.array_equal(res["Uf"], f["U"].astype(np.float64))),
+           "ratio_id": res["rid"] / o["res"]["id"], "ratio_cur": res["rcur"] / o["res"]["cur"],
+           "oracle_id": o["res"]["id"], "oracle_cur": o["res"]["cur"]}
+    if pj == K:
+        out["Z_rel_err"] = _rel(res["Z"], o["Z"])
+        if pi == K:
+            out["U_rel_err"] = _rel(res["U"], o["U"])
+    return out
+
+
+def configs_report(torch, R, ctx, reps=3):
+    """The two precision forms at their own sizes, end to end (GPU time per
+    call back to back; residuals of the last call):
+    * 16384 x 16384 stored BF16 (rank-512 Gaussian factors + 1e-4 N(0,1)),
+      k = 512, l = 544: BF16 sketch, FP32 LUPP, Z with one FP64 refinement
+      step, CUR, both residuals;
+    * 65536 x 4096 FP32, |F||G| (rank 384) + uniform[0, 1e-3], k = 384,
+      l = 400: FP8 sketch, FP32 LUPP, Z (one refinement), CUR, CUR residual."""
+    from paper_2104_05877_amd import inputs
+
+    def timed(fn):
+        out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    rep = {}
+    m = n = 16384
+    k, l = 512, 544
+    A = inputs.torch_lowrank_noise(m, n, k, 1e-4, 9, "cuda").T.contiguous().bfloat16().T
+    Om = inputs.torch_gaussian(l, m, 10, "cuda").T.contiguous().bfloat16().T
+
+    def c2():
+        X = R.rpid_sketch(ctx, A, Om)
+        J, Lf, Uf, _, _, _ = R.rpid_select_columns(ctx, X, k, sync=False)
+        Z, _ = R.rpid_id_coeffs(ctx, X, k, J, Lf, Uf, refine_steps=1)
+        I, U, _, st = R.rpid_cur(ctx, A, k, J)
+        return J, Z, I, U, st
+
+    (J, Z, I, U, st), ms = timed(c2)
+    rep["bf16_16384x16384_k512_l544"] = {
+        "ms_per_decomposition": ms, "status_rows": st,
+        "residual_id": R.rpid_residual(ctx, R.RESIDUAL_ID, A, k, J, Z=Z),
+        "residual_cur": R.rpid_residual(ctx, R.RESIDUAL_CUR, A, k, J, I=I, U=U)}
+    del A, Om, J, Z, I, U
+    torch.cuda.empty_cache()
+    m, n, k, l = 65536, 4096, 384, 400
+    A = inputs.torch_nonneg_lowrank(m, n, k, 1e-3, 5, "cuda")
+    Om = inputs.torch_gaussian(l, m, 6, "cuda", dtype=torch.float32)
+
+    def c3():
+        X = R.rpid_sketch_fp8(ctx, A, Om)
+        J, Lf, Uf, _, _, _ = R.rpid_select_columns(ctx, X, k, sync=False)
+        Z, _ = R.rpid_id_coeffs(ctx, X, k, J, Lf, Uf, refine_steps=1)
+        I, U, _, st = R.rpid_cur(ctx, A, k, J)
+        return J, Z, I, U, st
+
+    (J, Z, I, U, st), ms = timed(c3)
+    rep["fp8_65536x4096_k384_l400"] = {
+        "ms_per_decomposition": ms, "status_rows": st,
+        "residual_id": R.rpid_residual(ctx, R.RESIDUAL_ID, A, k, J, Z=Z),
+        "residual_cur": R.rpid_residual(ctx, R.RESIDUAL_CUR, A, k, J, I=I, U=U)}
+    del A, Om
+    torch.cuda.empty_cache()
+    return rep
 
 
 # learned-rank report: a seeded stream of matrices with exponential or
@@ -559,18 +732,20 @@ def main():
         return
     log("generating poly8192 inputs on the GPU")
     data = make_inputs(torch, args.seed, args.input_cache)
-    calibration_copy(torch)
+    hbm_measured = calibration_copy(torch)
+    log(f"calibration copy: {hbm_measured / 1e9:.0f} GB/s (read + write)")
     ctx = R.Context(0)
     if args.two_sided_only:
-        A, Om = data[args.mode]
+        A, Om = data[args.reports_mode]
         rep = two_sided_report(torch, R, ctx, A, Om, None)
         rep_qr = cpqr_report(torch, R, ctx, A, Om, None)
         rep_sp = sparse_report(torch, R, ctx, A, Om)
         ctx.close()
-        print(json.dumps({"mode": args.mode, "two_sided": rep, "cpqr": rep_qr, "sparse": rep_sp}), flush=True)
+        print(json.dumps({"mode": args.reports_mode, "two_sided": rep, "cpqr": rep_qr, "sparse": rep_sp}),
+              flush=True)
         return
     results = {}
-    order = [args.mode] + [m for m in ("bf16", "f32", "f64") if m != args.mode]
+    order = [args.mode] + [m for m in ("f64", "f32", "bf16") if m != args.mode]
     if args.only_main:
         order = [args.mode]
     for mode in order:
@@ -584,45 +759,65 @@ def main():
     main_r = results[args.mode]
     per = main_r["per_call_ms"]
     ctx2 = R.Context(0, stream=torch.cuda.Stream(device=0))
-    ov_ms, ov_out = overlapped_steps(torch, R, ctx, ctx2, *data[args.mode], args.steps, args.warmup)
+    ov = {}
+    for mode in order:
+        ov[mode] = overlapped_steps(torch, R, ctx, ctx2, *data[mode],
+                                    args.steps if mode == args.mode else args.other_steps,
+                                    args.warmup if mode == args.mode else 1)
     ctx2.close()
+    ov_ms, ov_out = ov[args.mode]
     ov_same = bool(np.array_equal(ov_out["J"].cpu().numpy(), main_r["J"])
                    and np.array_equal(ov_out["I"].cpu().numpy(), main_r["I"])
                    and ov_out["residual_id"] == main_r["rid"] and ov_out["residual_cur"] == main_r["rcur"])
     log(f"overlapped step: {ov_ms:.3f} ms (sequential {main_r['ms_per_step']:.3f}), same outputs {ov_same}")
     step_ms = main_r["ms_per_step"] if args.no_overlap else ov_ms
+    cold = cold_steps(torch, R, ctx, *data[args.mode], args.cold_steps) if args.cold_steps > 0 else None
     sk_loop_ms = sketch_loop(torch, R, ctx, *data[args.mode])
-    # Dominant single-kernel call of the main mode: sketch (GEMM + split-K sum)
-    # or the LUPP panel kernel (select_columns: two 8-byte fills + the kernel).
+
+    # The call with the largest time per step and its one dominant kernel:
+    # the sketch GEMM, the LUPP panel kernel (select_columns), or the
+    # residual product (residual_id / residual_cur).
     es = 8 if args.mode == "f64" else 4
-    lupp_bytes = N * K * es + N * K * es + K * K * es  # read panel, write L, write U
     a_es = {"f64": 8, "f32": 4, "bf16": 2}[args.mode]
-    sketch_bytes = M * N * a_es + L * M * a_es + L * N * (8 if args.mode == "f64" else 4)
-    sketch_flops = 2.0 * L * M * N
-    t_sk = per["sketch"] * 1e-3
-    t_lu = per["select_columns"] * 1e-3
-    sketch_mfma = sketch_flops / (sk_loop_ms * 1e-3) / PEAK_MFMA[args.mode]
-    if t_lu >= t_sk:
-        ach = lupp_bytes / t_lu
-        rec = recorded_traffic()
+    peak_mfma = PEAK_MFMA[args.mode]
+    cands = {
+        "select_columns": dict(kernel="lupp_panel_kernel (column LUPP of X^T, 8192 x 256)", bound="hbm",
+                               work=N * K * es + N * K * es + K * K * es,
+                               note="algorithmic bytes: panel read, L' and U' written"),
+        "sketch": dict(kernel="sketch GEMM (X = Omega A, 272 x 8192 x 8192)",
+                       bound="hbm" if args.mode == "bf16" else "mfma",
+                       work=(M * N * a_es + L * M * a_es + L * N * es) if args.mode == "bf16" else 2.0 * L * M * N,
+                       note="bf16: bytes of A, Omega and X; else 2lmn flops"),
+        "residual_id": dict(kernel="residual product ||A - C Z||_F (8192 x 8192, inner 256)",
+                            bound="hbm" if args.mode == "bf16" else "mfma",
+                            work=(M * N * a_es) if args.mode == "bf16" else 2.0 * M * N * K,
+                            note="bf16: bytes of A; else 2mnk flops"),
+        "residual_cur": dict(kernel="residual product ||A - (C U) R||_F (8192 x 8192, inner 256)",
+                             bound="hbm" if args.mode == "bf16" else "mfma",
+                             work=(M * N * a_es) if args.mode == "bf16" else 2.0 * M * N * K,
+                             note="bf16: bytes of A; else 2mnk flops"),
+    }
+    dom = max(cands, key=lambda c: per[c])
+    c = cands[dom]
+    t_dom = per[dom] * 1e-3
+    if c["bound"] == "hbm":
+        ach = c["work"] / t_dom
         traffic = None
-        if rec is not None and rec.get("mode") == args.mode:
-            traffic = rec["hbm_bytes_per_launch"]
-        roof = {"kernel": "lupp_panel_kernel (column LUPP of X^T, 8192 x 256)", "bound": "hbm",
-                "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": ach / PEAK_HBM, "traffic": traffic, "algorithmic_bytes": lupp_bytes,
-                "avg_ms": per["select_columns"], "us_per_pivot": per["select_columns"] * 1e3 / K}
+        if dom == "select_columns":
+            rec = recorded_traffic()
+            if rec is not None and rec.get("mode") == args.mode:
+                traffic = rec["hbm_bytes_per_launch"]
+        roof = {"kernel": c["kernel"], "call": dom, "bound": "hbm", "achieved": ach / 1e9,
+                "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
+                "frac_of_measured_hbm": ach / hbm_measured, "traffic": traffic,
+                "algorithmic_per_launch": c["work"], "algorithmic": c["note"], "avg_ms": per[dom]}
     else:
-        if args.mode == "bf16":
-            ach = sketch_bytes / t_sk
-            roof = {"kernel": "sketch_kernel + split_reduce (X = Omega A)", "bound": "hbm",
-                    "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                    "frac": ach / PEAK_HBM, "traffic": None, "avg_ms": per["sketch"]}
-        else:
-            ach = sketch_flops / t_sk
-            roof = {"kernel": "sketch_kernel + split_reduce (X = Omega A)", "bound": "mfma",
-                    "achieved": ach / 1e12, "peak": PEAK_MFMA[args.mode] / 1e12, "unit": "TFLOP/s",
-                    "frac": ach / PEAK_MFMA[args.mode], "traffic": None, "avg_ms": per["sketch"]}
+        ach = c["work"] / t_dom
+        roof = {"kernel": c["kernel"], "call": dom, "bound": "mfma", "achieved": ach / 1e12,
+                "peak": peak_mfma / 1e12, "unit": "TFLOP/s", "frac": ach / peak_mfma, "traffic": None,
+                "algorithmic_per_launch": c["work"], "algorithmic": c["note"], "avg_ms": per[dom]}
+    roof["lupp_us_per_pivot"] = per["select_columns"] * 1e3 / K
+    sketch_mfma = 2.0 * L * M * N / (sk_loop_ms * 1e-3) / peak_mfma
 
     line = {
         "metric": "ID+CUR decomps/sec & sketch-GEMM MFMA util at 8192^2, k=256; BF16 vs FP64",
@@ -645,29 +840,37 @@ def main():
         "step_ms_sequential": main_r["ms_per_step"],
         "step_ms_overlapped": ov_ms,
         "overlapped_outputs_equal_sequential": ov_same,
+        "cold_step_ms_p10_p50_p90": cold,
+        "hbm_measured_GBps": hbm_measured / 1e9,
         "sketch_mfma_util": sketch_mfma,
         "sketch_ms_back_to_back": sk_loop_ms,
-        "modes": {m: {"decomps_per_s": 1e3 / r["ms_per_step"], "ms_per_step": r["ms_per_step"],
+        "modes": {m: {"decomps_per_s": 1e3 / ov[m][0], "ms_per_step_overlapped": ov[m][0],
+                      "ms_per_step_sequential": r["ms_per_step"],
                       "step_ms_p10_p50_p90": r["step_ms_p10_p50_p90"],
                       "per_call_ms": r["per_call_ms"], "residual_id": r["rid"],
                       "residual_cur": r["rcur"]} for m, r in results.items()},
-        "speedup_bf16_vs_f64": (results["f64"]["ms_per_step"] / results["bf16"]["ms_per_step"]
-                                if "f64" in results and "bf16" in results else None),
+        "speedup_bf16_vs_f64": (ov["f64"][0] / ov["bf16"][0] if "f64" in ov and "bf16" in ov else None),
         "decomp_only": {m: {"decomps_per_s": 1e3 / r["decomp_ms_p10_p50_p90"][1],
                             "ms_p10_p50_p90": r["decomp_ms_p10_p50_p90"]} for m, r in results.items()},
         "roofline": roof,
     }
+    rdata = data[args.reports_mode]
+    rres = results.get(args.reports_mode, main_r)
     if not args.only_main:
-        log("power-iteration report (Rand-LUPP-1piter)")
-        line["power_iteration"] = power_report(torch, R, ctx, *data[args.mode], main_r)
+        log(f"power-iteration report (Rand-LUPP-1piter), {args.reports_mode} input")
+        line["power_iteration"] = power_report(torch, R, ctx, *rdata, rres)
         log("two-sided report (Alg. 3)")
-        line["two_sided"] = two_sided_report(torch, R, ctx, *data[args.mode], main_r)
+        line["two_sided"] = two_sided_report(torch, R, ctx, *rdata, rres)
         log("Rand-CPQR report")
-        line["cpqr"] = cpqr_report(torch, R, ctx, *data[args.mode], main_r)
+        line["cpqr"] = cpqr_report(torch, R, ctx, *rdata, rres)
         log("sparse-sketch report")
-        line["sparse"] = sparse_report(torch, R, ctx, *data[args.mode])
+        line["sparse"] = sparse_report(torch, R, ctx, *rdata)
         log("sketch on the larger sketch workloads")
         line["sketch_shapes"] = sketch_shapes_report(torch, R, ctx)
+        line["reports_mode"] = args.reports_mode
+    if not args.no_configs and not args.only_main:
+        log("precision forms at their own sizes")
+        line["configs"] = configs_report(torch, R, ctx)
     if not args.no_learned and not args.only_main:
         log("learned-rank report")
         line["learned_rank"] = learned_report(torch, ctx)
@@ -679,12 +882,35 @@ def main():
                                 "cores": cb["threads"], "kind": "oracle",
                                 "sample": "1 decomposition + ID/CUR residuals of poly8192 "
                                           f"({args.mode} storage values promoted to FP64), "
-                                          f"{cb['seconds']:.2f} s"}
-        line["residual_ratio_vs_oracle"] = {"id": main_r["rid"] / cb["rid"],
-                                            "cur": main_r["rcur"] / cb["rcur"],
-                                            "oracle_id": cb["rid"], "oracle_cur": cb["rcur"],
-                                            "J_equal": bool(np.array_equal(main_r["J"], cb["J"])),
-                                            "I_equal": bool(np.array_equal(main_r["I"], cb["I"]))}
+                                          f"{cb['seconds']:.2f} s on {cb['threads']} BLAS threads",
+                                "nproc": cb["nproc"], "cpu_model": cb["cpu_model"],
+                                "gflops": cb["gflops"], "seconds_1thread": cb["seconds_1thread"],
+                                "value_1thread": (1.0 / cb["seconds_1thread"]) if cb["seconds_1thread"] else None,
+                                "gflops_1thread": cb["gflops_1thread"],
+                                "flops_counted": "2mn(l + 3k): sketch, Q_C^T A, both residual products"}
+        if not args.no_parity:
+            log("parity of every mode against the FP64 oracle on the same stored values")
+            o32 = cb["oracle"]
+            o32["res"] = {"id": cb["rid"], "cur": cb["rcur"]}
+            par = {}
+            if args.mode in ("f64", "f32"):
+                for mode in ("f64", "f32"):
+                    if mode in results:
+                        par[mode] = parity_report(results[mode], o32, mode)
+            if "bf16" in results:
+                import oracle.rpid_oracle as O
+
+                ab = np.asfortranarray(data["bf16"][0].double().cpu().numpy())
+                omb = np.asfortranarray(data["bf16"][1].double().cpu().numpy())
+                ob = O.decompose(ab, omb, K)
+                ob["res"] = O.residuals(ab, ob["J"], Z=ob["Z"], I=ob["I"], U=ob["U"], only=("id", "cur"))
+                par["bf16"] = parity_report(results["bf16"], ob, "bf16")
+            line["parity"] = par
+            line["residual_ratio_vs_oracle"] = {
+                "id": main_r["rid"] / cb["rid"], "cur": main_r["rcur"] / cb["rcur"],
+                "oracle_id": cb["rid"], "oracle_cur": cb["rcur"],
+                "J_equal": bool(np.array_equal(main_r["J"], cb["oracle"]["J"])),
+                "I_equal": bool(np.array_equal(main_r["I"], cb["oracle"]["I"]))}
     ctx.close()
     print(json.dumps(line), flush=True)
 

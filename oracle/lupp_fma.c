@@ -28,8 +28,13 @@
  * Returns 0, t + 1 for an exactly zero pivot at step t (only t pivots are
  * defined), or -1 if S holds a NaN or an infinity.
  *
- * Build: cc -O2 -ffp-contract=off -fPIC -shared lupp_fma.c -o liblupp_fma.so -lm
- * (contraction off: the only fused operations are the explicit fma calls).
+ * The rows of one step are independent, so they are updated in parallel
+ * (OpenMP); every value is the same for any thread count.
+ *
+ * Build: cc -O2 -mfma -fopenmp -ffp-contract=off -fPIC -shared lupp_fma.c
+ *        -o liblupp_fma.so -lm
+ * (contraction off: the only fused operations are the explicit fma calls,
+ * which -mfma turns into the hardware instruction, itself a single rounding).
  */
 #include <math.h>
 #include <stdint.h>
@@ -77,6 +82,7 @@
       for (int64_t c = t; c < k; ++c) U[t * k + c] = S[p * k + c];                        \
       done[p] = 1;                                                                        \
       L[p * k + t] = (T)1;                                                                \
+      _Pragma("omp parallel for schedule(static)")                                        \
       for (int64_t i = 0; i < n; ++i) {                                                   \
         if (done[i]) continue;                                                            \
         const T m = S[i * k + t] / piv;                                                   \

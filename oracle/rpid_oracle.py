@@ -267,6 +267,7 @@ _FMA_LIB = None
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FMA_SRC = os.path.join(_HERE, "lupp_fma.c")
 FMA_LIB = os.path.join(_HERE, "liblupp_fma.so")
+FMA_CFLAGS = ["-O2", "-mfma", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared"]
 
 
 def build_fma_lib(force=False):
@@ -275,8 +276,7 @@ def build_fma_lib(force=False):
     if force or not os.path.exists(FMA_LIB) or os.path.getmtime(FMA_LIB) < os.path.getmtime(FMA_SRC):
         cc = os.environ.get("CC", "gcc")
         tmp = FMA_LIB + ".tmp%d" % os.getpid()
-        subprocess.run([cc, "-O2", "-ffp-contract=off", "-fPIC", "-shared", FMA_SRC, "-o", tmp, "-lm"],
-                       check=True, capture_output=True)
+        subprocess.run([cc, *FMA_CFLAGS, FMA_SRC, "-o", tmp, "-lm"], check=True, capture_output=True)
         os.replace(tmp, FMA_LIB)
     return FMA_LIB
 
@@ -451,12 +451,20 @@ def optimal_error(s, k):
 # --------------------------------------------------------------------------
 # The whole path of Alg. 2 with the sketch-based ID and stable CUR
 # --------------------------------------------------------------------------
-def decompose(A, Omega, k, gaps=False, want_cur=True):
+def decompose(A, Omega, k, gaps=False, want_cur=True, lupp="numpy", X=None):
     """Alg. 2 end to end: X = Omega A; LUPP on X -> J; Z; C = A(:, J);
-    LUPP on C -> I; U.  Returns a dict with every intermediate."""
+    LUPP on C -> I; U.  Returns a dict with every intermediate.
+    lupp="fma" takes both LUPPs from lupp_colwise_fma in float64 (no gaps);
+    X (optional) replaces the sketch (e.g. the FP8 form's)."""
     A = _f64(A)
-    X = sketch(A, Omega)
-    col = lupp_colwise(X, k, gaps=gaps)
+    X = sketch(A, Omega) if X is None else _f64(X)
+    if lupp == "fma":
+        if gaps:
+            raise ValueError("gaps need the numpy LUPP")
+        lupp_colwise_ = lambda X_, k_, gaps=False: lupp_colwise_fma(X_, k_, np.float64)  # noqa: E731
+    else:
+        lupp_colwise_ = lupp_colwise
+    col = lupp_colwise_(X, k, gaps=gaps)
     out = dict(X=X, J=col["J"], L=col["L"], Ufac=col["U"], diag=col["diag"],
                k_eff=col["k_eff"], status=col["status"])
     if gaps:
@@ -469,7 +477,7 @@ def decompose(A, Omega, k, gaps=False, want_cur=True):
     out["eta"] = eta(Z, J)
     if want_cur:
         C = A[:, J]
-        row = lupp_rowwise(C, k, gaps=gaps)
+        row = lupp_colwise_(C.T, k, gaps=gaps)
         out["I"] = row["J"]
         out["status_I"] = row["status"]
         if gaps:

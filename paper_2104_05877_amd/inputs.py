@@ -163,6 +163,19 @@ def torch_spectral(m, n, s, seed, device):
     return at.T
 
 
+def torch_poly8192(seed, device, m=8192, n=8192, l=272):
+    """The 8192 x 8192 benchmark workload: A = U diag(s) V^T with Haar U, V
+    and s_i = i^-2, generated in float64 and stored float32, and a Gaussian
+    embedding Omega (l x m) stored float32.  Returns (A32, Omega32),
+    column-major on ``device``."""
+    torch = _torch()
+    a64 = torch_spectral(m, n, poly_spectrum(min(m, n), 2.0), seed, device)
+    a32 = a64.T.contiguous().float().T
+    del a64
+    om32 = torch_gaussian(l, m, seed + 7, device).T.contiguous().float().T
+    return a32, om32
+
+
 def torch_gaussian(rows, cols, seed, device, dtype=None):
     """rows x cols iid N(0,1), column-major, float64 unless dtype given."""
     torch = _torch()

@@ -85,9 +85,10 @@ def test_sketch_fp8_tall_full_size_sampled(R, ctx):
 
 
 def test_lupp_tall_panel_invariants(R, ctx):
-    """FP32 LUPP of a 384 x 65536 panel (512 workgroups, two per CU): pivots
-    distinct, |L'| <= 1 with unit pivots, and X^T(:, 0:k) = L' U' (the row
-    order of L' is the original one) to FP32 accuracy."""
+    """FP32 LUPP of a 384 x 65536 panel (256 workgroups of 768 threads, two
+    threads per column, one workgroup per CU): pivots distinct, |L'| <= 1
+    with unit pivots, and X^T(:, 0:k) = L' U' (the row order of L' is the
+    original one) to FP32 accuracy."""
     l, n, k = 384, 65536, 384
     say("lupp tall panel", l, n, k)
     X = inputs.torch_gaussian(l, n, 21, "cuda", dtype=torch.float32)
@@ -228,3 +229,21 @@ def test_fp8_codes_ties_and_subnormals_exact(R, ctx, m, l):
     sel[0, :] = False
     assert np.array_equal(X[sel[rows]], expect[rows][sel[rows]])
     assert np.array_equal(X, O.sketch_fp8(A, Om))
+
+
+def test_lupp_grid_above_one_workgroup_per_cu_refused(R, ctx):
+    """A panel that would need more workgroups than compute units (FP64, k =
+    384, 65536 rows: 128 rows per workgroup at most) is refused on the host
+    with RPID_ERR_UNSUPPORTED; nothing is launched."""
+    say("lupp refused grid", 384, 65536)
+    X = inputs.torch_gaussian(384, 65536, 22, "cuda")
+    with pytest.raises(R.RpidError) as e:
+        R.rpid_select_columns(ctx, X, 384)
+    assert e.value.status == -103
+
+
+@pytest.mark.skip(reason="grids of more than one workgroup per compute unit are refused: one such "
+                         "launch (two workgroups per CU, FP32 384 x 65536 panel) once ran into the "
+                         "exchange's spin limit and the cause has not been shown")
+def test_lupp_two_workgroups_per_cu():
+    """Kept as a record of the refused configuration (see the reason)."""

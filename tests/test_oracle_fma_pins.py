@@ -196,8 +196,7 @@ def _mutant_lupp(tmp_path, name, old, new):
     path = tmp_path / ("m_%d.c" % abs(hash(name)))
     path.write_text(src.replace(old, new))
     so = str(path) + ".so"
-    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", str(path), "-o", so, "-lm"],
-                   check=True, capture_output=True)
+    subprocess.run(["gcc", *O.FMA_CFLAGS, str(path), "-o", so, "-lm"], check=True, capture_output=True)
     lib = ctypes.CDLL(so)
     P = ctypes.c_void_p
     for fn in ("lupp_fma_f64", "lupp_fma_f32"):
