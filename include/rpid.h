@@ -58,6 +58,7 @@ typedef enum {
 #define RPID_ERR_LAUNCH (-104)      /* cooperative launch could not co-schedule the grid */
 #define RPID_ERR_TIMEOUT (-105)     /* a device-side wait exceeded its spin limit */
 #define RPID_ERR_BREAKDOWN (-106)   /* Cholesky breakdown while orthonormalising C or R^T */
+#define RPID_ERR_SCRATCH (-107)     /* input larger than the fixed scratch of rpid_sketch_noalloc */
 
 typedef struct rpid_ctx_s* rpid_ctx;
 
@@ -86,6 +87,29 @@ int rpid_version(void);
 int rpid_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
                 const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo, void* X, rpid_dtype x_t,
                 int64_t ldx);
+
+/*
+ * rpid_sketch for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, types, kernels and result, but the call's scratch (the
+ * packed Omega^T, m l e_A bytes, and the split-K partial sums) lives in a
+ * fixed 64 MiB device array that the library holds on each device until the
+ * process ends, instead of the context's growable workspace.  The call
+ * performs no hipMalloc, hipFree or other allocation.
+ * Limits: m * l * e_A + 576 bytes must fit in 64 MiB (e_A = 8, 4, 2 for
+ * F64, F32, BF16), else RPID_ERR_SCRATCH before anything is enqueued; the
+ * split-K count is capped so that the partial sums fit (for larger l * n
+ * the summation order, and so the last bits of X, can differ from
+ * rpid_sketch's; where rpid_sketch's own split fits, X is bitwise the same).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (nothing in it has to start at zero); two calls that overlap on one
+ * device (contexts on different streams) race on it and must be ordered by
+ * the caller.
+ * Errors: as rpid_sketch, plus RPID_ERR_SCRATCH.
+ */
+int rpid_sketch_noalloc(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                        int64_t lda, const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo,
+                        void* X, rpid_dtype x_t, int64_t ldx);
 
 /*
  * Row sketch with one plain power iteration, eq. (def_power_iter) with q = 1

@@ -2,7 +2,9 @@
 // validation, workspace sizing and the order of the kernels of each step.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "rpid_internal.hpp"
 
@@ -385,6 +387,106 @@ static int residual_impl(rpid_ctx ctx, int which, const TA* A, rpid_dtype a_t, i
   return RPID_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free sketch entry point: the packed Omega^T
+// and the split-K partial sums live here instead of in the context's
+// workspace.  Each device holds its own copy; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device (the
+// array's name is a host-side stand-in).  Every call on a device shares it.
+static constexpr size_t kFixedScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;  // by device; null until looked up
+}  // namespace
+
+// This device's scratch address, looked up once per device (the device must
+// be current).
+static int fixed_scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize(device + 1, nullptr);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RPID_ERR_HIP;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return RPID_OK;
+}
+
+// Points the context's workspace at another buffer for the length of one
+// call (the carving helpers read ctx->ws / ctx->ws_bytes) and restores it.
+struct WorkspaceSwap {
+  rpid_ctx c;
+  void* ws;
+  size_t bytes;
+  WorkspaceSwap(rpid_ctx ctx, void* p, size_t b) : c(ctx), ws(ctx->ws), bytes(ctx->ws_bytes) {
+    c->ws = p;
+    c->ws_bytes = b;
+  }
+  ~WorkspaceSwap() {
+    c->ws = ws;
+    c->ws_bytes = bytes;
+  }
+};
+
+// X = Omega A (Alg. 2, step 2).  With `fixed` the call takes its scratch from
+// the device's fixed array (no allocation; inputs whose packed Omega^T does
+// not fit are refused, and the split-K count is capped so that the partial
+// sums fit), otherwise from the context's growable workspace.
+static int sketch_entry(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                        int64_t lda, const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo,
+                        void* X, rpid_dtype x_t, int64_t ldx, bool fixed) {
+  if (!ctx) return -1;
+  if (!A) return -2;
+  if (m < 1) return -4;
+  if (n < 1) return -5;
+  if (lda < m) return -6;
+  if (!Omega) return -7;
+  if (l < 1 || l > 1024) return -9;
+  if (ldo < l) return -10;
+  if (!X) return -11;
+  if (ldx < l) return -13;
+  const bool f64 = a_t == RPID_F64 && o_t == RPID_F64 && x_t == RPID_F64;
+  const bool f32 = a_t == RPID_F32 && o_t == RPID_F32 && x_t == RPID_F32;
+  const bool bf = a_t == RPID_BF16 && o_t == RPID_BF16 && x_t == RPID_F32;
+  if (!(f64 || f32 || bf)) return RPID_ERR_UNSUPPORTED;
+  const size_t es = esize(a_t);
+  const size_t acc = f64 ? 8 : 4;
+  Carve cv;
+  const size_t o_pt = cv.take<char>((size_t)m * l * es + 64);
+  const size_t ws_sk = cv.off;
+  int64_t max_split = 16;
+  if (fixed) {
+    if (!ctx->fixed_scratch) return RPID_ERR_HIP;
+    if (ws_sk + 512 > kFixedScratchBytes) return RPID_ERR_SCRATCH;
+    // partial sums start at the next 256-byte boundary
+    const size_t room = kFixedScratchBytes - ((ws_sk + 255) & ~(size_t)255);
+    const int64_t fit = (int64_t)(room / ((size_t)l * n * acc));
+    max_split = fit < 1 ? 1 : (fit > 16 ? 16 : fit);
+  }
+  RPID_HIP_CHECK(hipSetDevice(ctx->device));
+  if (!fixed) RPID_CHECK(ensure_workspace(ctx, ws_sk + sketch_workspace_bytes(ctx, m, n, l, (int)acc)));
+  WorkspaceSwap swap(ctx, fixed ? ctx->fixed_scratch : ctx->ws,
+                     fixed ? kFixedScratchBytes : ctx->ws_bytes);
+  // Pt = Omega^T, m x l column-major (rows of Omega contiguous)
+  if (f64) {
+    double* Pt = ws_ptr<double>(ctx, o_pt);
+    RPID_CHECK(transpose_copy<double>(ctx, l, m, (const double*)Omega, ldo, Pt, m));
+    return sketch_f64(ctx, Pt, m, (const double*)A, lda, m, n, l, (double*)X, ldx, ws_sk, max_split);
+  }
+  if (f32) {
+    float* Pt = ws_ptr<float>(ctx, o_pt);
+    RPID_CHECK(transpose_copy<float>(ctx, l, m, (const float*)Omega, ldo, Pt, m));
+    return sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk, max_split);
+  }
+  uint16_t* Pt = ws_ptr<uint16_t>(ctx, o_pt);
+  RPID_CHECK(transpose_copy<uint16_t>(ctx, l, m, (const uint16_t*)Omega, ldo, Pt, m));
+  return sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, l, (float*)X, ldx, ws_sk,
+                     max_split);
+}
+
 }  // namespace rpid
 
 using namespace rpid;
@@ -404,6 +506,7 @@ const char* rpid_status_string(int s) {
     case RPID_ERR_LAUNCH: return "cooperative launch could not co-schedule the grid";
     case RPID_ERR_TIMEOUT: return "device-side wait exceeded its spin limit";
     case RPID_ERR_BREAKDOWN: return "Cholesky breakdown while orthonormalising C or R^T";
+    case RPID_ERR_SCRATCH: return "input larger than the fixed scratch of the allocation-free call";
     default: return "invalid argument (status = -position)";
   }
 }
@@ -425,6 +528,11 @@ int rpid_create(rpid_ctx* out, int device, void* hip_stream) {
   }
   c->num_cu = prop.multiProcessorCount;
   if (hipHostMalloc((void**)&c->host_status, 64, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RPID_ERR_HIP;
+  }
+  if (fixed_scratch_address(device, &c->fixed_scratch) != RPID_OK) {
+    (void)hipHostFree(c->host_status);
     delete c;
     return RPID_ERR_HIP;
   }
@@ -477,40 +585,13 @@ int rpid_set_stream(rpid_ctx ctx, void* hip_stream) {
 int rpid_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
                 const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo, void* X, rpid_dtype x_t,
                 int64_t ldx) {
-  if (!ctx) return -1;
-  if (!A) return -2;
-  if (m < 1) return -4;
-  if (n < 1) return -5;
-  if (lda < m) return -6;
-  if (!Omega) return -7;
-  if (l < 1 || l > 1024) return -9;
-  if (ldo < l) return -10;
-  if (!X) return -11;
-  if (ldx < l) return -13;
-  const bool f64 = a_t == RPID_F64 && o_t == RPID_F64 && x_t == RPID_F64;
-  const bool f32 = a_t == RPID_F32 && o_t == RPID_F32 && x_t == RPID_F32;
-  const bool bf = a_t == RPID_BF16 && o_t == RPID_BF16 && x_t == RPID_F32;
-  if (!(f64 || f32 || bf)) return RPID_ERR_UNSUPPORTED;
-  RPID_HIP_CHECK(hipSetDevice(ctx->device));
-  const size_t es = esize(a_t);
-  Carve cv;
-  const size_t o_pt = cv.take<char>((size_t)m * l * es + 64);
-  const size_t ws_sk = cv.off;
-  RPID_CHECK(ensure_workspace(ctx, ws_sk + sketch_workspace_bytes(ctx, m, n, l, f64 ? 8 : 4)));
-  // Pt = Omega^T, m x l column-major (rows of Omega contiguous)
-  if (f64) {
-    double* Pt = ws_ptr<double>(ctx, o_pt);
-    RPID_CHECK(transpose_copy<double>(ctx, l, m, (const double*)Omega, ldo, Pt, m));
-    return sketch_f64(ctx, Pt, m, (const double*)A, lda, m, n, l, (double*)X, ldx, ws_sk);
-  }
-  if (f32) {
-    float* Pt = ws_ptr<float>(ctx, o_pt);
-    RPID_CHECK(transpose_copy<float>(ctx, l, m, (const float*)Omega, ldo, Pt, m));
-    return sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
-  }
-  uint16_t* Pt = ws_ptr<uint16_t>(ctx, o_pt);
-  RPID_CHECK(transpose_copy<uint16_t>(ctx, l, m, (const uint16_t*)Omega, ldo, Pt, m));
-  return sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, l, (float*)X, ldx, ws_sk);
+  return sketch_entry(ctx, A, a_t, m, n, lda, Omega, o_t, l, ldo, X, x_t, ldx, false);
+}
+
+int rpid_sketch_noalloc(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int64_t n,
+                        int64_t lda, const void* Omega, rpid_dtype o_t, int64_t l, int64_t ldo,
+                        void* X, rpid_dtype x_t, int64_t ldx) {
+  return sketch_entry(ctx, A, a_t, m, n, lda, Omega, o_t, l, ldo, X, x_t, ldx, true);
 }
 
 int rpid_sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda,

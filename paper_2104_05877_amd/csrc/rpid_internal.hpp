@@ -27,6 +27,9 @@ struct rpid_ctx_s {
   // call that can run beside the main stream's (fork and join by events).
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // Device address of this device's fixed scratch array (the allocation-free
+  // sketch entry point), looked up once per device at context creation.
+  void* fixed_scratch = nullptr;
 };
 
 namespace rpid {
@@ -123,14 +126,19 @@ size_t lupp_workspace_bytes(rpid_ctx ctx, int64_t n, int64_t k, int elem_bytes);
 
 // X = P^T A for a "row-contiguous" left operand: P is m x l column-major (ldp),
 // i.e. P^T is l x m with rows contiguous; A m x n (lda); X l x n (ldx).
+// `max_split` caps the number of split-K slices (each l x n accumulators in
+// the workspace at ws_off).
 int sketch_f64(rpid_ctx ctx, const double* Pt, int64_t ldp, const double* A, int64_t lda,
-               int64_t m, int64_t n, int64_t l, double* X, int64_t ldx, size_t ws_off);
+               int64_t m, int64_t n, int64_t l, double* X, int64_t ldx, size_t ws_off,
+               int64_t max_split = 16);
 int sketch_f32(rpid_ctx ctx, const float* Pt, int64_t ldp, const float* A, int64_t lda,
-               int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
+               int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off,
+               int64_t max_split = 16);
 int sketch_e4m3(rpid_ctx ctx, const uint8_t* Pt, int64_t ldp, const uint8_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
 int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
-                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off);
+                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off,
+                int64_t max_split = 16);
 // Y^T = Omega A^T (l x m) for a column-major m x n BF16 A read in place;
 // Ot = Omega^T is n x l (ldot).  RPID_ERR_UNSUPPORTED when the shape or the
 // alignment does not suit the kernel (n % 64, m % 8, 16-byte alignment).

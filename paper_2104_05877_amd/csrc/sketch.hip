@@ -936,7 +936,7 @@ bool residual_stream_bf16(rpid_ctx ctx, int64_t m, int64_t n, int64_t r, const u
 template <typename TE>
 static int sketch_impl(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int64_t lda,
                        int64_t m, int64_t n, int64_t l, typename MT<TE>::Acc* X, int64_t ldx,
-                       size_t ws_off) {
+                       size_t ws_off, int64_t max_split) {
   using M = MT<TE>;
   using Acc = typename M::Acc;
   constexpr int RTMAX = 17;  // up to 272 rows per l-chunk
@@ -952,7 +952,7 @@ static int sketch_impl(rpid_ctx ctx, const TE* Pt, int64_t ldp, const TE* A, int
   int64_t split = (int64_t)ctx->num_cu / base_wgs;
   const int64_t kblocks = (m + M::BK - 1) / M::BK;
   if (split > kblocks) split = kblocks;
-  if (split > 16) split = 16;
+  if (split > max_split) split = max_split;
   if (split < 1) split = 1;
   int64_t kchunk = ((kblocks + split - 1) / split) * M::BK;
   split = (m + kchunk - 1) / kchunk;
@@ -1005,30 +1005,34 @@ size_t sketch_workspace_bytes(rpid_ctx ctx, int64_t m, int64_t n, int64_t l, int
 }
 
 int sketch_f64(rpid_ctx ctx, const double* Pt, int64_t ldp, const double* A, int64_t lda,
-               int64_t m, int64_t n, int64_t l, double* X, int64_t ldx, size_t ws_off) {
-  return sketch_impl<double>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+               int64_t m, int64_t n, int64_t l, double* X, int64_t ldx, size_t ws_off,
+               int64_t max_split) {
+  return sketch_impl<double>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, max_split);
 }
 int sketch_f32(rpid_ctx ctx, const float* Pt, int64_t ldp, const float* A, int64_t lda,
-               int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+               int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off,
+               int64_t max_split) {
   int err = RPID_OK;
-  if (l >= 1 && l <= 1024 && sketch_stream<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err))
+  if (l >= 1 && l <= 1024 &&
+      sketch_stream<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err, max_split))
     return err;
-  return sketch_impl<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+  return sketch_impl<float>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, max_split);
 }
 int sketch_e4m3(rpid_ctx ctx, const uint8_t* Pt, int64_t ldp, const uint8_t* A, int64_t lda,
                 int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
   int err = RPID_OK;
   if (l >= 1 && l <= 1024 && sketch_stream<uint8_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err))
     return err;
-  return sketch_impl<uint8_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+  return sketch_impl<uint8_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, 16);
 }
 int sketch_bf16(rpid_ctx ctx, const uint16_t* Pt, int64_t ldp, const uint16_t* A, int64_t lda,
-                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off) {
+                int64_t m, int64_t n, int64_t l, float* X, int64_t ldx, size_t ws_off,
+                int64_t max_split) {
   int err = RPID_OK;
   if (l >= 1 && l <= 1024 &&
-      sketch_stream<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err))
+      sketch_stream<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, &err, max_split))
     return err;
-  return sketch_impl<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off);
+  return sketch_impl<uint16_t>(ctx, Pt, ldp, A, lda, m, n, l, X, ldx, ws_off, max_split);
 }
 
 // Y^T = Omega A^T (l x m) for a column-major m x n BF16 A, with Ot = Omega^T

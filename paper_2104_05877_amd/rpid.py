@@ -31,6 +31,7 @@ ERR = {
     -104: "LAUNCH",
     -105: "TIMEOUT",
     -106: "BREAKDOWN",
+    -107: "SCRATCH",
 }
 
 _lib = None
@@ -45,6 +46,7 @@ _SIGS = {
     "rpid_status_string": (ctypes.c_char_p, [_i]),
     "rpid_version": (_i, []),
     "rpid_sketch": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
+    "rpid_sketch_noalloc": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
     "rpid_sketch_power1": (_i, [_P, _P, _i, _I, _I, _I, _P, _i, _I, _I, _P, _i, _I]),
     "rpid_sketch_two_sided": (_i, [_P, _P, _i, _I, _I, _I, _P, _I, _P, _I, _I, _P, _I, _P, _I, _i]),
     "rpid_cur_sketch": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _P, _I]),
@@ -181,6 +183,21 @@ def rpid_sketch(ctx: Context, A: torch.Tensor, Omega: torch.Tensor, out_dtype=No
     s = lib().rpid_sketch(ctx.handle, pa, dtype_code(A), m, n, lda, po, dtype_code(Omega), l, ldo, px,
                           dtype_code(X), ldx)
     _check("rpid_sketch", s)
+    return X
+
+
+def rpid_sketch_noalloc(ctx: Context, A: torch.Tensor, Omega: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """X = Omega A into the caller's X (l x n, column-major; FP32 for BF16
+    inputs) with the library's fixed device scratch: the call allocates
+    nothing."""
+    pa, m, n, lda = colmajor(A)
+    po, l, m2, ldo = colmajor(Omega)
+    px, lx, nx, ldx = colmajor(X)
+    if m2 != m or lx != l or nx != n:
+        raise ValueError("shapes of A (m x n), Omega (l x m) and X (l x n) disagree")
+    s = lib().rpid_sketch_noalloc(ctx.handle, pa, dtype_code(A), m, n, lda, po, dtype_code(Omega), l,
+                                  ldo, px, dtype_code(X), ldx)
+    _check("rpid_sketch_noalloc", s)
     return X
 
 
