@@ -388,8 +388,8 @@ def sparse_report(torch, R, ctx, A, Om):
     G = inputs.torch_gaussian(L, ms_, 97, "cuda", dtype=torch.float32).T.contiguous().T
     X, ms_csc = timed(lambda: R.rpid_sketch_csc(ctx, Ac, G))
     r2, s2 = inputs.sparse_sign_draws(rng, ms_, L, 8)
-    _, ms_csc_ss = timed(lambda: R.rpid_sketch_csc_sparse_sign(ctx, Ac, torch.from_numpy(r2).cuda(),
-                                                               torch.from_numpy(s2).cuda(), L, 8 ** -0.5))
+    r2d, s2d = torch.from_numpy(r2).cuda(), torch.from_numpy(s2).cuda()
+    _, ms_csc_ss = timed(lambda: R.rpid_sketch_csc_sparse_sign(ctx, Ac, r2d, s2d, L, 8 ** -0.5))
     (J, _, _, _, _, _), ms_sel = timed(lambda: R.rpid_select_columns(ctx, X, K, sync=False), reps=3)
     return {"sparse_sign_dense_ms": ms_ss_dense, "gaussian_dense_ms": ms_gauss_dense, "srtt_dense_ms": ms_srtt_dense,
             "snn65536_nnz": int(len(va)), "csc_gaussian_sketch_ms": ms_csc, "csc_sparse_sign_sketch_ms": ms_csc_ss,

@@ -1084,20 +1084,12 @@ int rpid_sketch_csc_sparse_sign(rpid_ctx ctx, const int64_t* colptr, const int64
   if (!X) return -14;
   if (ldx < l) return -15;
   RPID_HIP_CHECK(hipSetDevice(ctx->device));
-  Carve cv;
-  const size_t o_g = cv.take<char>((size_t)l * m * esize(v_t));
-  RPID_CHECK(ensure_workspace(ctx, cv.off));
-  // the embedding itself (l x m, columns contiguous) for the column-wise CSC sketch
-  if (v_t == RPID_F64) {
-    double* g = ws_ptr<double>(ctx, o_g);
-    RPID_CHECK(expand_sparse_sign<double>(ctx, m, l, (int)zeta, rows, signs, g, 1, l, false));
-    RPID_CHECK(csc_sketch<double>(ctx, m, n, nnz, colptr, rowidx, (const double*)vals, g, l, l, (double*)X, ldx));
-    return scale_matrix<double>(ctx, l, n, (double*)X, ldx, scale);
-  }
-  float* g = ws_ptr<float>(ctx, o_g);
-  RPID_CHECK(expand_sparse_sign<float>(ctx, m, l, (int)zeta, rows, signs, g, 1, l, false));
-  RPID_CHECK(csc_sketch<float>(ctx, m, n, nnz, colptr, rowidx, (const float*)vals, g, l, l, (float*)X, ldx));
-  return scale_matrix<float>(ctx, l, n, (float*)X, ldx, (float)scale);
+  // the embedding is applied as a sparse operator: O(nnz zeta) work, nothing expanded
+  if (v_t == RPID_F64)
+    return csc_sparse_sign<double>(ctx, m, n, nnz, colptr, rowidx, (const double*)vals, rows, signs,
+                                   (int)zeta, l, scale, (double*)X, ldx);
+  return csc_sparse_sign<float>(ctx, m, n, nnz, colptr, rowidx, (const float*)vals, rows, signs, (int)zeta,
+                                l, (float)scale, (float*)X, ldx);
 }
 
 int rpid_csc_gather(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, const void* vals,

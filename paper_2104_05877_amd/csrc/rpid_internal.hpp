@@ -163,6 +163,12 @@ template <typename T>
 int csc_sketch(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
                const int64_t* rowidx, const T* vals, const T* Gamma, int64_t ldg, int64_t l, T* X,
                int64_t ldx);
+// X = scale S A for a CSC matrix A and the sparse sign embedding S (l x m,
+// zeta entries +-1 per column given by rows / signs), applied directly.
+template <typename T>
+int csc_sparse_sign(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                    const int64_t* rowidx, const T* vals, const int32_t* rows, const int8_t* signs,
+                    int zeta, int64_t l, T scale, T* X, int64_t ldx);
 // C(:, t) = A(:, J[t]) for a CSC matrix (J null: all n columns, k = n).
 template <typename T>
 int csc_gather(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,

@@ -12,6 +12,8 @@
 //    MFMA hardware it is again cheapest as a dense l x m embedding, built from
 //    its definition (sincos in FP64, stored in A's type) and fed to the dense
 //    sketch.
+//  * For a sparse A in CSC form the sparse sign embedding is applied as the
+//    sparse operator it is (csc_sparse_sign_kernel below), O(nnz zeta).
 //  * The CSC sketch X = Gamma A runs one workgroup per column of A: every
 //    thread keeps up to four rows of X(:, j) in registers and adds
 //    Gamma(:, i) a_ij for the column's nonzeros in order (deterministic), so
@@ -159,6 +161,69 @@ __global__ __launch_bounds__(256) void csc_sketch_kernel(int64_t m, int64_t n, i
   }
 }
 
+// X(:, j) = scale * sum over the nonzeros a_ij of column j of S(:, i) a_ij for
+// the sparse sign embedding S (zeta entries +-1 per column: rows[i zeta + s],
+// signs[i zeta + s]) applied directly, O(nnz zeta) work: one wave per column
+// of A keeps X(:, j) in LDS; its lanes take 64 / zeta nonzeros per round
+// (lane = q zeta + s: nonzero q, entry s; four rounds' loads at once) and add
+// sign * a_ij into row
+// rows[i zeta + s] with LDS atomics issued nonzero by nonzero in storage
+// order, so every row receives its terms in the same order on every run (LDS
+// operations of one wave complete in order; the zeta rows of one column of
+// S are distinct).  The additions are those of the expanded embedding (each
+// term +-a_ij exact, one rounding per addition), and the scale is applied
+// once at the end.  Rows of A outside [0, m), rows of S outside [0, l) and
+// pointer ranges outside [0, nnz) are skipped.
+template <typename T>
+__global__ __launch_bounds__(256) void csc_sparse_sign_kernel(int64_t m, int64_t n, int64_t nnz,
+                                                              const int64_t* colptr,
+                                                              const int64_t* rowidx, const T* vals,
+                                                              const int32_t* rows, const int8_t* signs,
+                                                              int zeta, int l, T scale, T* X,
+                                                              int64_t ldx) {
+  __shared__ T acc[4][1024];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + wv;
+  if (j >= n) return;
+  T* a = acc[wv];
+  for (int r = lane; r < l; r += 64) a[r] = T(0);
+  int64_t p0 = colptr[j], p1 = colptr[j + 1];
+  p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
+  p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
+  const int per = 64 / zeta;  // nonzeros per round
+  const int q = lane / zeta, s = lane - q * zeta;
+  // NR rounds at a time: all their loads are in flight together (two
+  // dependent levels: the nonzeros, then their rows of S), then the adds
+  constexpr int NR = 4;
+  for (int64_t b = p0; b < p1; b += (int64_t)NR * per) {
+    int64_t i[NR];
+    T v[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int64_t p = b + (int64_t)u * per + q;
+      const bool ok = q < per && p < p1;
+      i[u] = ok ? rowidx[p] : -1;
+      v[u] = ok ? vals[p] : T(0);
+    }
+    int32_t r[NR];
+    int sg[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const bool ok = i[u] >= 0 && i[u] < m;
+      r[u] = ok ? rows[i[u] * zeta + s] : -1;
+      sg[u] = ok ? (int)signs[i[u] * zeta + s] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const bool ok = r[u] >= 0 && r[u] < l && sg[u] != 0;
+      const T c = sg[u] > 0 ? v[u] : -v[u];
+      for (int qq = 0; qq < per; ++qq)
+        if (ok && q == qq) atomicAdd(&a[r[u]], c);
+    }
+  }
+  for (int r = lane; r < l; r += 64) X[r + j * ldx] = a[r] * scale;
+}
+
 // C(:, t) = A(:, J[t]) densified (J null: every column, t = j); row indices
 // outside [0, m) are skipped.
 template <typename T>
@@ -251,6 +316,23 @@ template int csc_sketch<double>(rpid_ctx, int64_t, int64_t, int64_t, const int64
                                 const double*, const double*, int64_t, int64_t, double*, int64_t);
 template int csc_sketch<float>(rpid_ctx, int64_t, int64_t, int64_t, const int64_t*, const int64_t*,
                                const float*, const float*, int64_t, int64_t, float*, int64_t);
+
+template <typename T>
+int csc_sparse_sign(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,
+                    const int64_t* rowidx, const T* vals, const int32_t* rows, const int8_t* signs,
+                    int zeta, int64_t l, T scale, T* X, int64_t ldx) {
+  if (l < 1 || l > 1024 || n < 1 || zeta < 1 || zeta > 64) return RPID_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL((csc_sparse_sign_kernel<T>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, ctx->stream, m,
+                     n, nnz, colptr, rowidx, vals, rows, signs, zeta, (int)l, scale, X, ldx);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+template int csc_sparse_sign<double>(rpid_ctx, int64_t, int64_t, int64_t, const int64_t*, const int64_t*,
+                                     const double*, const int32_t*, const int8_t*, int, int64_t, double,
+                                     double*, int64_t);
+template int csc_sparse_sign<float>(rpid_ctx, int64_t, int64_t, int64_t, const int64_t*, const int64_t*,
+                                    const float*, const int32_t*, const int8_t*, int, int64_t, float,
+                                    float*, int64_t);
 
 template <typename T>
 int csc_gather(rpid_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* colptr,

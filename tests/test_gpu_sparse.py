@@ -214,3 +214,42 @@ def test_srtt_rand_lupp_fp64(R, ctx):
         assert abs(rid - ro) <= 1e-9 * ro
     else:
         assert rid <= 1.05 * ro
+
+
+@pytest.mark.parametrize("dt", ["float64", "float32"])
+@pytest.mark.parametrize("zeta,l", [(8, 300), (3, 64), (1, 17), (64, 64)])
+def test_csc_sparse_sign_direct_is_the_expanded_product(R, ctx, dt, zeta, l):
+    """The sparse sign embedding applied as a sparse operator to a CSC matrix
+    gives, bit for bit, the CSC sketch with the same embedding written out
+    densely (each term +-a_ij exact, the terms of a row added in the storage
+    order of the column, the scale applied once), and the same bits on a
+    second call (the additions are ordered).  SNN1e3 and a 3000 x 2000 matrix
+    with empty columns; zeta from 1 to 64 (one nonzero per wave round)."""
+    tdt = getattr(torch, dt)
+    rng = np.random.default_rng(40 + zeta)
+    cases = [(snn1e3(31), 1000, 1000)]
+    A2 = np.zeros((3000, 2000))
+    mask = rng.random((3000, 2000)) < 0.002
+    A2[mask] = rng.standard_normal(int(mask.sum()))
+    A2[:, ::7] = 0.0
+    from scipy.sparse import csc_matrix
+
+    sp = csc_matrix(A2)
+    sp.sort_indices()
+    cases.append(((sp.indptr.astype(np.int64), sp.indices.astype(np.int64), sp.data.astype(np.float64)), 3000,
+                  2000))
+    for (cp, ri, va), m, n in cases:
+        say("csc sparse sign direct", dt, m, n, "nnz", len(va), "zeta", zeta, "l", l)
+        A = to_dev_csc(R, cp, ri, va, m, n, tdt)
+        rows, signs = inputs.sparse_sign_draws(rng, m, l, zeta)
+        scale = 1.0 / np.sqrt(zeta)
+        X1 = R.rpid_sketch_csc_sparse_sign(ctx, A, torch.from_numpy(rows).cuda(), torch.from_numpy(signs).cuda(),
+                                           l, scale)
+        X2 = R.rpid_sketch_csc_sparse_sign(ctx, A, torch.from_numpy(rows).cuda(), torch.from_numpy(signs).cuda(),
+                                           l, scale)
+        S = O.sparse_sign_matrix(rows, signs, l)
+        Sd = dev(S, tdt)
+        Xe = R.rpid_sketch_csc(ctx, A, Sd) * torch.tensor(scale, dtype=tdt)
+        torch.cuda.synchronize()
+        assert torch.equal(X1, X2)
+        assert torch.equal(X1, Xe), float((X1 - Xe).abs().max())
