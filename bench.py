@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--sketch-shapes-only", action="store_true",
                     help="run only the sketch report on the 16384^2 BF16 and 65536 x 4096 FP8 "
                          "shapes (for profiling; no poly8192 input)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned-rank report (no poly8192 input)")
     ap.add_argument("--input-cache", default=None,
                     help="folder: load the FP32 workload from it if stored there, else "
                          "generate it and store it (lets profiled runs skip the QR-based "
@@ -647,64 +649,124 @@ def configs_report(torch, R, ctx, reps=3):
     return rep
 
 
-# learned-rank report: a seeded stream of matrices with exponential or
-# polynomial spectra; tolerance 1e-4 on the relative ID residual
-LEARN = dict(m_range=(1024, 2048), n_range=(1024, 2048), rate_range=(0.1, 1.0),
-             power_range=(2.5, 6.0))
-LEARN_TOL, LEARN_LMAX, LEARN_TRAIN, LEARN_TEST = 1e-4, 128, 128, 48
+# learned-rank report on the learned form's own workload: a seeded stream of
+# matrices with m, n uniform in [2048, 8192] and exponential (rate log-uniform
+# in [1e-3, 1e-1]) or polynomial (power uniform in [0.5, 3]) spectra, BF16
+# sketches of l = 512 rows, tolerance 1e-4 on the relative ID residual.  The
+# first 80 % of the stream (by index) trains the network (its last
+# LEARN_CALIB matrices calibrate the output shift), the last 20 % is held out.
+LEARN_TOL, LEARN_L, LEARN_N, LEARN_CALIB, LEARN_K0 = 1e-4, 512, 400, 64, 8
 
 
 def learned_report(torch, ctx):
-    """Train the rank network on LEARN_TRAIN matrices of the stream (labels
-    from the plain FP64 path), then reach the tolerance on LEARN_TEST held-out
-    matrices two ways: the BF16-profile network with the plain path as
-    fallback, and the plain FP64 path with rank doubling from 8.  Both answers
-    are evaluated by the FP64 residual; times are wall-clock per matrix."""
+    """Labels k* (smallest rank whose FP64 ID meets the tolerance, up to the
+    library's rank cap, by bisection on one FP64 sketch) for every matrix;
+    the network trained on the training part; then, on each held-out matrix,
+    the tolerance reached three ways, each answer checked by the FP64
+    residual: BF16 profile + network + plain path from k_hat (doubling on a
+    miss, past l up to the cap), the plain FP64 path with rank doubling from
+    LEARN_K0, and the pivot-ratio threshold rule on the same profile.  Times
+    are wall-clock per matrix, the BF16 copies of A and Omega included in
+    the two profile-based paths."""
     import numpy as np
 
     from paper_2104_05877_amd import inputs, learned as Lr
 
-    feats, targets, labels = [], [], []
-    for idx in range(LEARN_TRAIN):
-        A64, Om64, A16, Om16, _ = inputs.torch_stream_case(idx, LEARN_LMAX, "cuda", 1, **LEARN)
-        k, _ = Lr.rank_label(ctx, A64, Om64, LEARN_TOL, LEARN_LMAX)
-        feats.append(Lr.profile_features(ctx, A16, Om16, LEARN_LMAX))
+    cap = Lr.RANK_CAP
+    n_test = LEARN_N // 5
+    n_train = LEARN_N - n_test
+    n_fit = n_train - LEARN_CALIB
+
+    def case(idx):
+        A64, Om64, _, _, fam = inputs.torch_stream_case(idx, cap, "cuda", 0, with_lo=False)
+        return A64, Om64, fam
+
+    def lo_copies(A64, Om64):
+        return A64.T.contiguous().bfloat16().T, Om64[:LEARN_L].T.contiguous().bfloat16().T
+
+    t0 = time.perf_counter()
+    feats, labels = [], []
+    for idx in range(n_train):
+        A64, Om64, _ = case(idx)
+        k, _ = Lr.rank_label(ctx, A64, Om64, LEARN_TOL, cap)
+        A16, Om16 = lo_copies(A64, Om64)
+        feats.append(Lr.profile_features(ctx, A16, Om16, LEARN_L))
         labels.append(k)
-        targets.append(Lr.target_of(k, LEARN_LMAX))
+        del A64, Om64, A16, Om16
+        if (idx + 1) % 40 == 0:
+            log(f"learned: labelled {idx + 1} of {n_train} training matrices ({time.perf_counter() - t0:.0f} s)")
+    t_labels = time.perf_counter() - t0
+    F = torch.stack(feats)
+    T = torch.tensor([Lr.target_of(k, cap) for k in labels], dtype=torch.float32, device="cuda")
     net = Lr.RankNet(ctx, seed=1)
     t0 = time.perf_counter()
-    hist = net.fit(torch.stack(feats), torch.tensor(targets, dtype=torch.float32, device="cuda"),
-                   epochs=300, batch=32, lr=2e-3, tau=0.9, seed=2)
+    hist = net.fit(F[:n_fit].contiguous(), T[:n_fit].contiguous(), epochs=300, batch=32, lr=2e-3, tau=0.5,
+                   seed=2)
+    y_cal = net.predict(F[n_fit:].contiguous()).cpu().tolist()
+    shift = Lr.calibrate_shift(y_cal, labels[n_fit:], cap)
     t_train = time.perf_counter() - t0
-    res = dict(learned=[], doubling=[], att_l=[], att_d=[], khat=[], kfin=[], kstar=[], met=0)
-    for idx in range(10000, 10000 + LEARN_TEST):
-        A64, Om64, A16, Om16, _ = inputs.torch_stream_case(idx, LEARN_LMAX, "cuda", 1, **LEARN)
-        kd, ed, sd = Lr.solve_doubling(ctx, A64, Om64, LEARN_TOL, 8, LEARN_LMAX)
-        kl, el, sl, khat = Lr.solve_learned(ctx, net, A64, Om64, A16, Om16, LEARN_TOL, LEARN_LMAX,
-                                            LEARN_LMAX)
-        ks, _ = Lr.rank_label(ctx, A64, Om64, LEARN_TOL, LEARN_LMAX)
-        res["learned"].append(sl)
-        res["doubling"].append(sd)
-        res["att_l"].append(el)
-        res["att_d"].append(ed)
-        if kl is not None and ks is not None:
-            res["khat"].append(khat / ks)
-            res["kfin"].append(kl / ks)
-        res["met"] += int(kl is not None and khat >= kl)
+    log(f"learned: {n_train} training matrices labelled in {t_labels:.1f} s, shift {shift:+.2f}")
+
+    r = {key: [] for key in ("t_l", "t_d", "t_t", "a_l", "a_d", "a_t", "khat_ratio", "kl_ratio", "kd_ratio",
+                             "kt_ratio", "ks")}
+    met, same_outcome = 0, 0
+    for idx in range(n_train, LEARN_N):
+        A64, Om64, fam = case(idx)
+        ks, _ = Lr.rank_label(ctx, A64, Om64, LEARN_TOL, cap)
+        kd, ad, sd = Lr.solve_doubling(ctx, A64, Om64, LEARN_TOL, LEARN_K0, cap)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        A16, Om16 = lo_copies(A64, Om64)
+        torch.cuda.synchronize()
+        t_copy = time.perf_counter() - tc
+        kl, al, sl, khat = Lr.solve_learned(ctx, net, A64, Om64, A16, Om16, LEARN_TOL, LEARN_L, cap, shift)
+        kt, at, st, _ = Lr.solve_threshold(ctx, A64, Om64, A16, Om16, LEARN_TOL, LEARN_L, cap)
+        r["t_l"].append(sl + t_copy)
+        r["t_d"].append(sd)
+        r["t_t"].append(st + t_copy)
+        r["a_l"].append(al)
+        r["a_d"].append(ad)
+        r["a_t"].append(at)
+        r["ks"].append(ks)
+        same_outcome += int((kl is None) == (kd is None) == (kt is None))
+        if ks is not None:
+            met += int(khat >= ks)
+            r["khat_ratio"].append(khat / ks)
+            for key, kk in (("kl_ratio", kl), ("kd_ratio", kd), ("kt_ratio", kt)):
+                if kk is not None:
+                    r[key].append(kk / ks)
+        else:
+            met += int(khat >= cap)
+        del A64, Om64, A16, Om16
+        if (idx + 1 - n_train) % 20 == 0:
+            log(f"learned: {idx + 1 - n_train} of {n_test} held-out matrices solved")
+    all_labels = labels + r["ks"]
+
+    def med(v):
+        return float(np.median(v)) if v else None
+
     return {
-        "workload": "stream of %d + %d matrices, m, n in [%d, %d], exp rate in [%g, %g] or poly power "
-                    "in [%g, %g], tol %g, l = %d" % (LEARN_TRAIN, LEARN_TEST, *LEARN["m_range"],
-                                                     *LEARN["rate_range"], *LEARN["power_range"],
-                                                     LEARN_TOL, LEARN_LMAX),
-        "train_loss_first_last": [hist[0], hist[-1]], "train_seconds": t_train,
-        "ms_per_matrix_learned": 1e3 * float(np.mean(res["learned"])),
-        "ms_per_matrix_fp64_doubling": 1e3 * float(np.mean(res["doubling"])),
-        "speedup_learned_vs_fp64_doubling": float(np.sum(res["doubling"]) / np.sum(res["learned"])),
-        "fp64_attempts_learned": float(np.mean(res["att_l"])),
-        "fp64_attempts_doubling": float(np.mean(res["att_d"])),
-        "met_without_fallback": res["met"] / LEARN_TEST,
-        "khat_over_kstar_median": float(np.median(res["khat"])) if res["khat"] else None,
-        "kfinal_over_kstar_median": float(np.median(res["kfin"])) if res["kfin"] else None,
+        "workload": "stream of %d matrices (%d train incl. %d calibration, %d held out), m, n uniform in "
+                    "[2048, 8192], exp rate log-uniform in [1e-3, 1e-1] or poly power uniform in [0.5, 3], "
+                    "BF16 sketch l = %d, tol %g, ranks up to %d" % (LEARN_N, n_train, LEARN_CALIB, n_test, LEARN_L,
+                                                                    LEARN_TOL, cap),
+        "censored_beyond_l": float(np.mean([k is None or k > LEARN_L for k in all_labels])),
+        "censored_beyond_cap": float(np.mean([k is None for k in all_labels])),
+        "label_seconds_train": t_labels, "train_seconds": t_train,
+        "train_loss_first_last": [hist[0], hist[-1]], "calibrated_shift_log2": shift,
+        "ms_per_matrix_learned": 1e3 * float(np.mean(r["t_l"])),
+        "ms_per_matrix_fp64_doubling": 1e3 * float(np.mean(r["t_d"])),
+        "ms_per_matrix_threshold_rule": 1e3 * float(np.mean(r["t_t"])),
+        "speedup_learned_vs_fp64_doubling": float(np.sum(r["t_d"]) / np.sum(r["t_l"])),
+        "speedup_threshold_vs_fp64_doubling": float(np.sum(r["t_d"]) / np.sum(r["t_t"])),
+        "fp64_attempts_learned": float(np.mean(r["a_l"])),
+        "fp64_attempts_doubling": float(np.mean(r["a_d"])),
+        "fp64_attempts_threshold": float(np.mean(r["a_t"])),
+        "met_without_fallback": met / n_test,
+        "same_outcome_all_three": same_outcome / n_test,
+        "khat_over_kstar_median": med(r["khat_ratio"]),
+        "kfinal_over_kstar_median": {"learned": med(r["kl_ratio"]), "doubling": med(r["kd_ratio"]),
+                                     "threshold": med(r["kt_ratio"])},
     }
 
 
@@ -729,6 +791,12 @@ def main():
         rep = sketch_shapes_report(torch, R, ctx)
         ctx.close()
         print(json.dumps({"sketch_shapes": rep}), flush=True)
+        return
+    if args.learned_only:
+        ctx = R.Context(0)
+        rep = learned_report(torch, ctx)
+        ctx.close()
+        print(json.dumps({"learned_rank": rep}), flush=True)
         return
     log("generating poly8192 inputs on the GPU")
     data = make_inputs(torch, args.seed, args.input_cache)

@@ -192,7 +192,9 @@ int tri_solve(rpid_ctx ctx, int64_t k, int64_t nrhs, const double* T, int64_t ld
               bool lower_op, bool unit, const TB* B, int64_t brs, int64_t bcs, double* X,
               int64_t xrs, int64_t xcs);
 
-// W = T^{-1} for a k x k triangular T (k <= 512), lower or upper, unit or not.
+// W = T^{-1} for a k x k triangular T (k <= 1024), lower or upper, unit or
+// not; above 512 the scratch region at ws_tmp must also hold a
+// (k/2) x (k - k/2) FP64 product and the split-K parts of two GEMMs.
 int tri_inverse(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, bool lower, bool unit,
                 double* W, int64_t ldw, size_t ws_tmp);
 

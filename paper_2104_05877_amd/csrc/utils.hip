@@ -506,6 +506,16 @@ __global__ void axpy_kernel(int64_t rows, int64_t cols, double alpha, const doub
   }
 }
 
+__global__ void zero_block_kernel(int64_t rows, int64_t cols, double* D, int64_t ldd) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i, j;
+    split_index(e, rows, i, j);
+    D[i + j * ldd] = 0.0;
+  }
+}
+
 // Power iteration x <- G x / ||G x|| from x0 = (1, ..., 1) (G symmetric PSD),
 // stopped when the Rayleigh quotient changes by less than rtol (relative).
 __global__ __launch_bounds__(1024) void power_iter_kernel(int64_t k, const double* G, int64_t ldg,
@@ -669,6 +679,36 @@ int tri_inverse(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, bool lowe
                 double* W, int64_t ldw, size_t ws_tmp) {
   if (k < 1) return RPID_OK;
   if (sweep_supported(k)) return tri_inverse_sweep(ctx, k, T, ldt, lower, unit, W, ldw, ws_tmp);
+  if (k > 512 && k <= 1024) {
+    // 2 x 2 blocks of orders h and k - h (both <= 512): the diagonal blocks of
+    // W are the inverses of T's, the off-diagonal block is
+    //   lower: W21 = -W22 (T21 W11),   upper: W12 = -W11 (T12 W22),
+    // and the other off-diagonal block is zero.
+    const int64_t h = k / 2, h2 = k - h;
+    Carve cv;
+    cv.off = ws_tmp;
+    const size_t o_P = cv.take<double>((size_t)h * h2);
+    const size_t o_rest = cv.off;
+    RPID_CHECK(ws_check(ctx, o_rest));
+    double* P = ws_ptr<double>(ctx, o_P);
+    const double* T22 = T + h + h * ldt;
+    double* W22 = W + h + h * ldw;
+    RPID_CHECK(tri_inverse(ctx, h, T, ldt, lower, unit, W, ldw, o_rest));
+    RPID_CHECK(tri_inverse(ctx, h2, T22, ldt, lower, unit, W22, ldw, o_rest));
+    if (lower) {
+      RPID_CHECK(dgemm(ctx, false, false, h2, h, h, 1.0, T + h, ldt, W, ldw, 0.0, P, h2, o_rest));
+      RPID_CHECK(dgemm(ctx, false, false, h2, h, h2, -1.0, W22, ldw, P, h2, 0.0, W + h, ldw, o_rest));
+      hipLaunchKernelGGL(zero_block_kernel, dim3(grid_for(h * h2)), dim3(256), 0, ctx->stream, h, h2,
+                         W + h * ldw, ldw);
+    } else {
+      RPID_CHECK(dgemm(ctx, false, false, h, h2, h2, 1.0, T + h * ldt, ldt, W22, ldw, 0.0, P, h, o_rest));
+      RPID_CHECK(dgemm(ctx, false, false, h, h2, h, -1.0, W, ldw, P, h, 0.0, W + h * ldw, ldw, o_rest));
+      hipLaunchKernelGGL(zero_block_kernel, dim3(grid_for(h * h2)), dim3(256), 0, ctx->stream, h2, h,
+                         W + h, ldw);
+    }
+    RPID_HIP_CHECK(hipGetLastError());
+    return RPID_OK;
+  }
   const unsigned blocks = (unsigned)((k + 3) / 4);
   if (k <= 256)
     hipLaunchKernelGGL((tri_inverse_kernel<4, 8>), dim3(blocks), dim3(256), 0, ctx->stream, (int)k, T,

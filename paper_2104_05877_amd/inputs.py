@@ -236,13 +236,16 @@ def stream_spec(index, seed=0, m_range=(2048, 8192), n_range=(2048, 8192),
     return m, n, spec, fam
 
 
-def torch_stream_case(index, lmax, device, seed=0, **ranges):
+def torch_stream_case(index, lmax, device, seed=0, with_lo=True, **ranges):
     """Matrix `index` of the stream on the GPU: (A64, Omega64 (lmax x m),
-    A_bf16, Omega_bf16, family), column-major."""
+    A_bf16, Omega_bf16, family), column-major (the BF16 copies are None when
+    with_lo is false)."""
     torch = _torch()
     m, n, spec, fam = stream_spec(index, seed, **ranges)
     a64 = torch_spectral(m, n, spec, 100003 * (seed + 1) + 7 * index, device)
     om64 = torch_gaussian(lmax, m, 200003 * (seed + 1) + 11 * index, device)
+    if not with_lo:
+        return a64, om64, None, None, fam
     a16 = a64.T.contiguous().bfloat16().T
     om16 = om64.T.contiguous().bfloat16().T
     return a64, om64, a16, om16, fam

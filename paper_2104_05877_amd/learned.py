@@ -23,18 +23,25 @@ import torch
 from . import rpid as R
 
 FEAT = R.MLP_IN  # 512 profile entries
+RANK_CAP = 1024  # largest rank the library's LUPP, Z and residual accept
 
 
 # ---------------------------------------------------------------------------
 # features and labels
 # ---------------------------------------------------------------------------
-def profile_features(ctx, A_lo, Om_lo, l):
-    """Features of one matrix: sketch X = Omega A in the storage type of A_lo
-    (BF16 gives an FP32 sketch), LUPP over all l steps, profile
-    f_t = max(log10(|u_tt| / |u_00|), -20) (FEAT entries, -20 beyond k_eff)."""
+def profile(ctx, A_lo, Om_lo, l):
+    """Sketch X = Omega A in the storage type of A_lo (BF16 gives an FP32
+    sketch) and its LUPP over all l steps: (features, |u_tt| on the device,
+    k_eff); the features are f_t = max(log10(|u_tt| / |u_00|), -20) (FEAT
+    entries, -20 beyond k_eff)."""
     X = R.rpid_sketch(ctx, A_lo, Om_lo[:l])
     J, Lf, Uf, diag, keff, st = R.rpid_select_columns(ctx, X, l)
-    return R.rpid_mlp_features(ctx, diag, FEAT, keff)
+    return R.rpid_mlp_features(ctx, diag, FEAT, keff), diag, keff
+
+
+def profile_features(ctx, A_lo, Om_lo, l):
+    """The network's input for one matrix (see profile)."""
+    return profile(ctx, A_lo, Om_lo, l)[0]
 
 
 class PlainPath:
@@ -167,23 +174,67 @@ def solve_doubling(ctx, A64, Om64, tol, k0, lmax):
     return k, evals, time.perf_counter() - t0
 
 
-def predict_rank(ctx, net, A_lo, Om_lo, l_feat, lmax):
+def rank_of(y, shift, lmax):
+    """k_hat = ceil(2^(y + shift)) clamped to [1, lmax]."""
+    return int(min(max(math.ceil(2.0 ** (float(y) + shift)), 1), lmax))
+
+
+def predict_rank(ctx, net, A_lo, Om_lo, l_feat, lmax, shift=0.0):
     """k_hat from the profile of a low-precision sketch (clamped to [1, lmax])."""
     f = profile_features(ctx, A_lo, Om_lo, l_feat)
-    yhat = float(net.predict(f.view(1, FEAT))[0])
-    return int(min(max(math.ceil(2.0 ** yhat), 1), lmax))
+    return rank_of(net.predict(f.view(1, FEAT))[0], shift, lmax)
 
 
-def solve_learned(ctx, net, A64, Om64, A_lo, Om_lo, tol, l_feat, lmax):
+def solve_learned(ctx, net, A64, Om64, A_lo, Om_lo, tol, l_feat, lmax, shift=0.0):
     """Profile of the BF16 sketch's FP32 LUPP -> network -> k_hat, then the
-    plain FP64 path from k_hat with rank doubling as the fallback:
-    (k, attempts, seconds, k_hat)."""
+    plain FP64 path from k_hat with rank doubling as the fallback (up to
+    lmax, which may exceed l_feat): (k, attempts, seconds, k_hat)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    k_hat = predict_rank(ctx, net, A_lo, Om_lo, l_feat, lmax)
+    k_hat = predict_rank(ctx, net, A_lo, Om_lo, l_feat, lmax, shift)
     k, evals = _double_until(ctx, A64, Om64, tol, k_hat, lmax)
     torch.cuda.synchronize()
     return k, evals, time.perf_counter() - t0, k_hat
+
+
+def solve_threshold(ctx, A64, Om64, A_lo, Om_lo, tol, l_feat, lmax):
+    """Non-learned comparison: the same profile, k from the pivot-ratio rule
+    (threshold_rank), then the plain FP64 path with rank doubling:
+    (k, attempts, seconds, k_rule)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, diag, keff = profile(ctx, A_lo, Om_lo, l_feat)
+    k_rule = threshold_rank(diag[:max(keff, 1)].double().cpu().tolist(), tol)
+    k, evals = _double_until(ctx, A64, Om64, tol, min(k_rule, lmax), lmax)
+    torch.cuda.synchronize()
+    return k, evals, time.perf_counter() - t0, k_rule
+
+
+def modelled_cost(k_start, label, lmax, c0=32.0):
+    """Cost, in rank units, of reaching the tolerance from k_start with rank
+    doubling: an attempt at rank k costs k + c0 (sketch, LUPP steps and
+    residual all grow with k); a censored label (None) runs up to lmax."""
+    target = lmax if label is None else label
+    k, cost = k_start, 0.0
+    while True:
+        cost += k + c0
+        if k >= target or k >= lmax:
+            return cost
+        k = min(2 * k, lmax)
+
+
+def calibrate_shift(y_pred, labels, lmax, grid=None):
+    """The shift (log2 units) added to the network's outputs that minimises
+    the summed modelled cost over a calibration set the network was not
+    fitted on (a miss costs a doubling, an overshoot costs rank)."""
+    if grid is None:
+        grid = np.arange(-1.0, 2.0001, 0.05)
+    best = None
+    for d in grid:
+        c = sum(modelled_cost(rank_of(y, d, lmax), lab, lmax) for y, lab in zip(y_pred, labels))
+        if best is None or c < best[0]:
+            best = (c, float(d))
+    return best[1]
 
 
 def threshold_rank(diag, tol):

@@ -203,3 +203,24 @@ def test_learned_rank_gain(R, ctx, L):
     say("attempts learned", np.mean(att_l), "doubling", np.mean(att_d),
         "time learned", np.sum(t_l), "doubling", np.sum(t_d), "under-predictions", misses)
     assert np.mean(att_l) < np.mean(att_d)
+
+
+def test_fallback_beyond_sketch_rows(R, ctx, L):
+    """A matrix whose rank for the tolerance lies between the profile's
+    l = 512 and the library's rank cap: rank doubling and the label both go
+    past 512, the label is a crossing of the tolerance, and the answer of
+    the fallback meets it."""
+    say("fallback beyond l")
+    m, n = 2600, 2400
+    s = np.exp(-0.013 * np.arange(min(m, n)))
+    A64 = inputs.torch_spectral(m, n, s, 4242, "cuda")
+    Om64 = inputs.torch_gaussian(L.RANK_CAP, m, 4243, "cuda")
+    k, evals = L.rank_label(ctx, A64, Om64, TOL, L.RANK_CAP)
+    say("label", k, "evals", evals)
+    assert k is not None and 512 < k <= L.RANK_CAP
+    assert L.PlainPath(ctx, A64, Om64, L.RANK_CAP).residual(k) <= TOL
+    assert L.PlainPath(ctx, A64, Om64, L.RANK_CAP).residual(k - 1) > TOL
+    kd, ad, _ = L.solve_doubling(ctx, A64, Om64, TOL, 8, L.RANK_CAP)
+    say("doubling", kd, ad)
+    assert kd is not None and kd >= k and L.attempt(ctx, A64, Om64, kd) <= TOL
+

@@ -266,6 +266,31 @@ def test_large_k_f64_end_to_end(R, ctx, m, n, k, l, seed):
     assert abs(rcur - ro["cur"]) <= 1e-9 * ro["cur"]
 
 
+@pytest.mark.parametrize("m,n,k,seed", [(2600, 2200, 600, 11), (2100, 2300, 1024, 12)])
+def test_id_beyond_512_f64(R, ctx, m, n, k, seed):
+    """The interpolative decomposition at ranks above 512 (the triangular
+    inverse behind Z is assembled from two half-order inverses): J bit-exact,
+    Z within its conditioning, the ID residual to 1e-9 relative."""
+    say("id beyond 512", m, n, k)
+    A, Om = inputs.small_spectral_case(m, n, k, k, inputs.poly_spectrum(min(m, n), 1.0), seed)
+    X = O.sketch(A, Om)
+    f = O.lupp_colwise(X, k, gaps=True)
+    assert f["gap"].min() > 1e-9
+    Zo = O.id_coeffs(X, f["J"], k)
+    Ad = dev(A)
+    Xd = R.rpid_sketch(ctx, Ad, dev(Om))
+    J, Lf, Uf, diag, keff, st = R.rpid_select_columns(ctx, Xd, k)
+    assert st == 0 and keff == k
+    assert np.array_equal(host(J).astype(np.int64), f["J"])
+    Z, _ = R.rpid_id_coeffs(ctx, Xd, k, J, Lf, Uf, refine_steps=0)
+    kappa = np.linalg.cond(X[:k][:, f["J"]])
+    np.testing.assert_allclose(host(Z), Zo, rtol=0, atol=1e-13 * kappa * max(1.0, np.abs(Zo).max()))
+    ro = O.residuals(A, f["J"], Z=Zo, only=("id",))["id"]
+    rg = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, J, Z=Z)
+    say("residual gpu", rg, "oracle", ro, "kappa", kappa)
+    assert abs(rg - ro) <= 1e-9 * ro
+
+
 @pytest.mark.parametrize("m,n,k,seed", [(300, 257, 16, 1), (1500, 900, 100, 2)])
 def test_exact_recovery_gpu(R, ctx, m, n, k, seed):
     """rank(A) = k, l = k: the GPU's ID and CUR residuals are at round-off."""
