@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--sketch-shapes-only", action="store_true",
                     help="run only the sketch report on the 16384^2 BF16 and 65536 x 4096 FP8 "
                          "shapes (for profiling; no poly8192 input)")
+    ap.add_argument("--sparse-only", action="store_true",
+                    help="run only the CSC sketches of the SNN matrix, without the pivoting "
+                         "(for profiling; no poly8192 input)")
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned-rank report (no poly8192 input)")
     ap.add_argument("--input-cache", default=None,
@@ -382,6 +385,31 @@ def sparse_report(torch, R, ctx, A, Om):
     perm, phi, sel = inputs.srtt_draws(rng, m, L)
     pd, fd, sd = torch.from_numpy(perm).cuda(), torch.from_numpy(phi).cuda(), torch.from_numpy(sel).cuda()
     _, ms_srtt_dense = timed(lambda: R.rpid_sketch_srtt(ctx, A, pd, fd, sd))
+    rep = {"sparse_sign_dense_ms": ms_ss_dense, "gaussian_dense_ms": ms_gauss_dense, "srtt_dense_ms": ms_srtt_dense}
+    rep.update(csc_report(torch, R, ctx, rng))
+    return rep
+
+
+def csc_report(torch, R, ctx, rng, with_selection=True):
+    """CSC sketches of the SNN matrix 65536 x 65536 (r = 400, s_i = 2/i for
+    i <= 100 then 1/i, 0.1 % nonzeros, FP32 values, l = 272) with a Gaussian
+    and with a sparse sign embedding (zeta = 8, applied as a sparse operator),
+    then Rand-LUPP's column selection on the Gaussian sketch."""
+    import numpy as np
+
+    from paper_2104_05877_amd import inputs
+
+    def timed(fn, reps=20):
+        out = fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
     ms_ = 65536
     i = np.arange(1, 401, dtype=np.float64)
     sv = np.where(i <= 100, 2.0 / i, 1.0 / i)
@@ -392,11 +420,12 @@ def sparse_report(torch, R, ctx, A, Om):
     r2, s2 = inputs.sparse_sign_draws(rng, ms_, L, 8)
     r2d, s2d = torch.from_numpy(r2).cuda(), torch.from_numpy(s2).cuda()
     _, ms_csc_ss = timed(lambda: R.rpid_sketch_csc_sparse_sign(ctx, Ac, r2d, s2d, L, 8 ** -0.5))
-    (J, _, _, _, _, _), ms_sel = timed(lambda: R.rpid_select_columns(ctx, X, K, sync=False), reps=3)
-    return {"sparse_sign_dense_ms": ms_ss_dense, "gaussian_dense_ms": ms_gauss_dense, "srtt_dense_ms": ms_srtt_dense,
-            "snn65536_nnz": int(len(va)), "csc_gaussian_sketch_ms": ms_csc, "csc_sparse_sign_sketch_ms": ms_csc_ss,
-            "csc_select_columns_ms": ms_sel,
-            "csc_gaussian_gflops": 2.0 * len(va) * L / (ms_csc * 1e-3) / 1e9}
+    rep = {"snn65536_nnz": int(len(va)), "csc_gaussian_sketch_ms": ms_csc, "csc_sparse_sign_sketch_ms": ms_csc_ss,
+           "csc_gaussian_gflops": 2.0 * len(va) * L / (ms_csc * 1e-3) / 1e9}
+    if with_selection:
+        (J, _, _, _, _, _), ms_sel = timed(lambda: R.rpid_select_columns(ctx, X, K, sync=False), reps=3)
+        rep["csc_select_columns_ms"] = ms_sel
+    return rep
 
 
 def calibration_copy(torch, reps=5):
@@ -791,6 +820,14 @@ def main():
         rep = sketch_shapes_report(torch, R, ctx)
         ctx.close()
         print(json.dumps({"sketch_shapes": rep}), flush=True)
+        return
+    if args.sparse_only:
+        import numpy as np
+
+        ctx = R.Context(0)
+        rep = csc_report(torch, R, ctx, np.random.default_rng(99), with_selection=False)
+        ctx.close()
+        print(json.dumps({"sparse": rep}), flush=True)
         return
     if args.learned_only:
         ctx = R.Context(0)

@@ -267,9 +267,10 @@ int rpid_sketch_csc(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx, 
  * embedding costs is O(nnz zeta)): each nonzero a_ij adds +-a_ij into the zeta
  * rows of X(:, j) named by rows[i, :], nothing of size l x m is formed.
  * Deterministic: every row of X(:, j) receives its terms in the storage
- * order of column j (the zeta rows of one column of the embedding must be
- * distinct, as the definition has them; repeated rows are not an error but
- * then lose that property).  No workspace.
+ * order of column j, so the result has the bits of the CSC sketch with the
+ * embedding written out densely (the zeta rows of one column of the
+ * embedding must be distinct, as the definition has them; repeated rows are
+ * not an error but then lose that property).  No workspace.
  */
 int rpid_sketch_csc_sparse_sign(rpid_ctx ctx, const int64_t* colptr, const int64_t* rowidx,
                                 const void* vals, rpid_dtype v_t, int64_t m, int64_t n, int64_t nnz,

@@ -217,15 +217,18 @@ def test_srtt_rand_lupp_fp64(R, ctx):
 
 
 @pytest.mark.parametrize("dt", ["float64", "float32"])
-@pytest.mark.parametrize("zeta,l", [(8, 300), (3, 64), (1, 17), (64, 64)])
+@pytest.mark.parametrize("zeta,l", [(8, 300), (3, 64), (1, 17), (64, 64), (8, 1024)])
 def test_csc_sparse_sign_direct_is_the_expanded_product(R, ctx, dt, zeta, l):
     """The sparse sign embedding applied as a sparse operator to a CSC matrix
     gives, bit for bit, the CSC sketch with the same embedding written out
     densely (each term +-a_ij exact, the terms of a row added in the storage
-    order of the column, the scale applied once), and the same bits on a
-    second call (the additions are ordered).  SNN1e3 and a 3000 x 2000 matrix
-    with empty columns; zeta from 1 to 64 (one nonzero per wave round)."""
+    order of the column, the scale applied once), the same bits on a second
+    call, and lies within 2(m + 2)u scale |S||A| of the oracle.  SNN1e3 and a
+    3000 x 2000 matrix with empty columns (n not a multiple of the columns a
+    wave takes); zeta from 1 to 64 (one nonzero per wave round); l up to
+    1024 (the largest LDS footprint)."""
     tdt = getattr(torch, dt)
+    u = 2.0**-53 if dt == "float64" else 2.0**-24
     rng = np.random.default_rng(40 + zeta)
     cases = [(snn1e3(31), 1000, 1000)]
     A2 = np.zeros((3000, 2000))
@@ -243,13 +246,15 @@ def test_csc_sparse_sign_direct_is_the_expanded_product(R, ctx, dt, zeta, l):
         A = to_dev_csc(R, cp, ri, va, m, n, tdt)
         rows, signs = inputs.sparse_sign_draws(rng, m, l, zeta)
         scale = 1.0 / np.sqrt(zeta)
-        X1 = R.rpid_sketch_csc_sparse_sign(ctx, A, torch.from_numpy(rows).cuda(), torch.from_numpy(signs).cuda(),
-                                           l, scale)
-        X2 = R.rpid_sketch_csc_sparse_sign(ctx, A, torch.from_numpy(rows).cuda(), torch.from_numpy(signs).cuda(),
-                                           l, scale)
+        rd, sd = torch.from_numpy(rows).cuda(), torch.from_numpy(signs).cuda()
+        X1 = R.rpid_sketch_csc_sparse_sign(ctx, A, rd, sd, l, scale)
+        X2 = R.rpid_sketch_csc_sparse_sign(ctx, A, rd, sd, l, scale)
         S = O.sparse_sign_matrix(rows, signs, l)
-        Sd = dev(S, tdt)
-        Xe = R.rpid_sketch_csc(ctx, A, Sd) * torch.tensor(scale, dtype=tdt)
+        Xe = R.rpid_sketch_csc(ctx, A, dev(S, tdt)) * torch.tensor(scale, dtype=tdt)
         torch.cuda.synchronize()
         assert torch.equal(X1, X2)
+        Ad = O.csc_dense(cp, ri, host(A.vals), m, n)
+        ref = O.sketch_sparse_sign(Ad, rows, signs, l, scale)
+        bound = 2 * (m + 2) * u * scale * (np.abs(S) @ np.abs(Ad)) + 1e-300
+        assert np.all(np.abs(host(X1) - ref) <= bound)
         assert torch.equal(X1, Xe), float((X1 - Xe).abs().max())
