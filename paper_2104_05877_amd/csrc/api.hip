@@ -233,11 +233,29 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   RPID_CHECK(gather_columns<TA, double>(ctx, m, k, A, lda, n, J, C64, m));
   if (!f64) RPID_CHECK(gather_columns<TA, float>(ctx, m, k, A, lda, n, J, ws_ptr<float>(ctx, o_C32), m));
 
+  // The fork point: C is ready.  The row LUPP (a cooperative launch, which
+  // cannot start until every compute unit can take one of its workgroups) is
+  // enqueued before the side stream's work, so it starts on an idle device
+  // and the side's small kernels fit beside it.
+  RPID_HIP_CHECK(hipEventRecord(ctx->ev_fork, ctx->stream));
+
+  // (S6) row-wise LUPP on C gives I.  Its status goes to slot 4 and is read
+  // with the Cholesky statuses at the end (one host synchronisation per
+  // call): after a zero pivot the rest runs on the zero-filled tail of I,
+  // which only reads valid rows of A.
+  int64_t* lupp_status = status_dev + 4;
+  if (f64) {
+    RPID_CHECK(lupp_panel<double>(ctx, C64, 1, m, m, k, I, ws_ptr<double>(ctx, o_Lc), m,
+                                  ws_ptr<double>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
+  } else {
+    RPID_CHECK(lupp_panel<float>(ctx, ws_ptr<float>(ctx, o_C32), 1, m, m, k, I, ws_ptr<float>(ctx, o_Lc), m,
+                                 ws_ptr<float>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
+  }
+
   // Side stream: everything that needs C but not I -- Cholesky-QR2 of C
   // (Q_C, the inverses of its two factors, Tc = their product) and
   // W = Q_C^T A -- runs beside the row LUPP.  Only C (read) is shared; the
   // side's regions and scratch are its own.
-  RPID_HIP_CHECK(hipEventRecord(ctx->ev_fork, ctx->stream));
   RPID_HIP_CHECK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
   SideJoin side_join(ctx);
   {
@@ -265,19 +283,6 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
       RPID_HIP_CHECK(hipGetLastError());
     }
     RPID_HIP_CHECK(hipEventRecord(ctx->ev_join, ctx->stream));
-  }
-
-  // (S6) row-wise LUPP on C gives I.  Its status goes to slot 4 and is read
-  // with the Cholesky statuses at the end (one host synchronisation per
-  // call): after a zero pivot the rest runs on the zero-filled tail of I,
-  // which only reads valid rows of A.
-  int64_t* lupp_status = status_dev + 4;
-  if (f64) {
-    RPID_CHECK(lupp_panel<double>(ctx, C64, 1, m, m, k, I, ws_ptr<double>(ctx, o_Lc), m,
-                                  ws_ptr<double>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
-  } else {
-    RPID_CHECK(lupp_panel<float>(ctx, ws_ptr<float>(ctx, o_C32), 1, m, m, k, I, ws_ptr<float>(ctx, o_Lc), m,
-                                 ws_ptr<float>(ctx, o_Uc), k, nullptr, o_tmp, lupp_status));
   }
 
   // (S7) R^T = A(I, :)^T (n x k), Cholesky-QR2 into Q_R (in Rt), Tr; then,
