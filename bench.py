@@ -495,10 +495,11 @@ def _counter_rows(folder):
     return list(per.values())
 
 
-def summarize_counters(fetch_dir, write_dir):
+def summarize_counters(fetch_dir, write_dir, mode):
     """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the LUPP launches of a
-    --only-main bf16 run, scaled by what the same counters read for the
-    calibration copy (CALIB_MIB MiB read, CALIB_MIB MiB written)."""
+    --only-main run in `mode`, scaled by what the same counters read for the
+    calibration copy (CALIB_MIB MiB read, CALIB_MIB MiB written); recorded
+    per mode."""
     out = {}
     for name, folder in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _counter_rows(folder)
@@ -513,25 +514,33 @@ def summarize_counters(fetch_dir, write_dir):
                      "lupp_bytes_per_launch": sum(lupp) / len(lupp) * 1024.0 * factor}
     with open(LUPP_SOURCE, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    rec = {"kernel": "lupp_panel_kernel<float> on 8192 x 256 panels (bf16 mode)", "mode": "bf16",
+    elem = "double" if mode == "f64" else "float"
+    rec = {"kernel": f"lupp_panel_kernel<{elem}> on 8192 x 256 panels ({mode} mode)", "mode": mode,
            "source_sha256": sha, "counters": out,
            "hbm_bytes_per_launch": out["fetch"]["lupp_bytes_per_launch"]
            + out["write"]["lupp_bytes_per_launch"]}
+    try:
+        with open(TRAFFIC_FILE) as f:
+            allrec = json.load(f)
+    except (OSError, ValueError):
+        allrec = {}
+    allrec[mode] = rec
     with open(TRAFFIC_FILE, "w") as f:
-        json.dump(rec, f, indent=1)
+        json.dump(allrec, f, indent=1)
     print(json.dumps(rec, indent=1))
 
 
-def recorded_traffic():
-    """Counter-measured HBM bytes per LUPP launch, if recorded for this source."""
+def recorded_traffic(mode):
+    """Counter-measured HBM bytes per LUPP launch in `mode`, if recorded for
+    this source."""
     try:
         with open(TRAFFIC_FILE) as f:
-            rec = json.load(f)
+            rec = json.load(f).get(mode)
         with open(LUPP_SOURCE, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError):
+    except (OSError, ValueError, AttributeError):
         return None
-    if rec.get("source_sha256") != sha:
+    if not rec or rec.get("source_sha256") != sha:
         return None
     return rec
 
@@ -802,7 +811,7 @@ def learned_report(torch, ctx):
 def main():
     args = parse()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters)
+        summarize_counters(*args.summarize_counters, args.mode)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
@@ -909,8 +918,8 @@ def main():
         ach = c["work"] / t_dom
         traffic = None
         if dom == "select_columns":
-            rec = recorded_traffic()
-            if rec is not None and rec.get("mode") == args.mode:
+            rec = recorded_traffic(args.mode)
+            if rec is not None:
                 traffic = rec["hbm_bytes_per_launch"]
         roof = {"kernel": c["kernel"], "call": dom, "bound": "hbm", "achieved": ach / 1e9,
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach / PEAK_HBM,
