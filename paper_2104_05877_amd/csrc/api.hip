@@ -187,6 +187,14 @@ struct SideJoin {
   }
 };
 
+// Split-K caps of the W = Q_C^T A sketch.  Its workgroups each fill a CU for
+// their whole life; with the FP64 grid capped at three quarters of the CUs
+// (split 3 of the 64 column strips' 4), the R-side Cholesky-QR2 that runs
+// beside it keeps a quarter of the device instead of queueing behind all of
+// W (measured: FP64 CUR 2.53 -> 2.35 ms at 8192^2, k = 256; the FP32 and BF16
+// sketches of W gained nothing from a cap).
+static constexpr int64_t W_SPLIT_F64 = 3, W_SPLIT_F32 = 16, W_SPLIT_BF16 = 16;
+
 // ---------------------------------------------------------------------------
 template <typename TA>
 static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_t n, int64_t lda,
@@ -267,18 +275,18 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
     RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, Wi, k, Wi + 2 * kk, k, 0.0, Tc, k, o_tmp2));
     // W = Q_C^T A (k x n), in the arithmetic of A's storage
     if (a_t == RPID_F64) {
-      RPID_CHECK(sketch_f64(ctx, Qc, m, (const double*)A, lda, m, n, k, W, k, o_tmp2));
+      RPID_CHECK(sketch_f64(ctx, Qc, m, (const double*)A, lda, m, n, k, W, k, o_tmp2, W_SPLIT_F64));
     } else if (a_t == RPID_F32) {
       float* Pt = ws_ptr<float>(ctx, o_Pt);
       float* W32 = ws_ptr<float>(ctx, o_W2);
       RPID_CHECK(convert_matrix<double, float>(ctx, m, k, Qc, m, Pt, m));
-      RPID_CHECK(sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, k, W32, k, o_tmp2));
+      RPID_CHECK(sketch_f32(ctx, Pt, m, (const float*)A, lda, m, n, k, W32, k, o_tmp2, W_SPLIT_F32));
       RPID_CHECK(convert_matrix<float, double>(ctx, k, n, W32, k, W, k));
     } else {
       uint16_t* Pt = ws_ptr<uint16_t>(ctx, o_Pt);
       float* W2 = ws_ptr<float>(ctx, o_W2);
       RPID_CHECK(split_bf16(ctx, m, k, Qc, m, 2, Pt, m));
-      RPID_CHECK(sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, 2 * k, W2, 2 * k, o_tmp2));
+      RPID_CHECK(sketch_bf16(ctx, Pt, m, (const uint16_t*)A, lda, m, n, 2 * k, W2, 2 * k, o_tmp2, W_SPLIT_BF16));
       hipLaunchKernelGGL(sum_halves_kernel, dim3(4096), dim3(256), 0, ctx->stream, k, n, W2, W);
       RPID_HIP_CHECK(hipGetLastError());
     }
