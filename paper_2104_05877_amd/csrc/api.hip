@@ -207,7 +207,6 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   const size_t o_C32 = f64 ? 0 : cv.take<float>((size_t)m * k);
   const size_t o_Lc = cv.take<double>((size_t)m * k);  // LUPP multipliers (discarded)
   const size_t o_Uc = cv.take<double>((size_t)k * k);
-  const size_t o_Rg = cv.take<double>((size_t)k * n);
   const size_t o_Rt = cv.take<double>((size_t)n * k);
   const size_t o_C2 = cv.take<double>((size_t)m * k);
   const size_t o_Qc = cv.take<double>((size_t)m * k);
@@ -298,8 +297,7 @@ static int cur_impl(rpid_ctx ctx, const TA* A, rpid_dtype a_t, int64_t m, int64_
   // (U = R_C^{-1} (Q_C^T A Q_R) R_R^{-T}, R_C^{-1} = W1c W2c, R_R^{-1} = W1r W2r).
   // A breakdown leaves garbage, never a fault, in what follows; the statuses
   // are checked once at the end.
-  RPID_CHECK(gather_rows<TA, double>(ctx, k, n, A, lda, m, I, ws_ptr<double>(ctx, o_Rg), k));
-  RPID_CHECK(transpose_f64(ctx, k, n, ws_ptr<double>(ctx, o_Rg), k, Rt, n));
+  RPID_CHECK(gather_rows_t<TA>(ctx, k, n, A, lda, m, I, Rt, n));
   double* Rt2 = ws_ptr<double>(ctx, o_Rt2);
   RPID_CHECK(chol_qr_one(ctx, n, k, Rt, Rt2, F + kk, Wi + kk, status_dev + 1, o_tmp));
   RPID_CHECK(chol_qr_one(ctx, n, k, Rt2, Rt, F + 3 * kk, Wi + 3 * kk, status_dev + 3, o_tmp));

@@ -239,6 +239,10 @@ int axpy_matrix(rpid_ctx ctx, int64_t rows, int64_t cols, double alpha, const do
 int power_iteration(rpid_ctx ctx, int64_t k, const double* G, int64_t ldg, int max_iter,
                     double rtol, double* lam);
 // Y (cols x rows) = X^T for an FP64 rows x cols matrix.
+// Rt(j, t) = A(I[t], j) as FP64 (Rt n x k, ldr >= n): the rows A(I, :) transposed.
+template <typename TS>
+int gather_rows_t(rpid_ctx ctx, int64_t k, int64_t n, const TS* A, int64_t lda, int64_t nrows,
+                  const int64_t* I, double* Rt, int64_t ldr);
 int transpose_f64(rpid_ctx ctx, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                   double* Y, int64_t ldy);
 // D = S + diag(shift) on a k x k matrix; `shift_from` (device, nullable)

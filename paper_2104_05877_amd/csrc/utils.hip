@@ -84,6 +84,21 @@ __global__ void gather_rows_kernel(int64_t k, int64_t n, const TS* A, int64_t ld
   }
 }
 
+// Rt(j, t) = A(I[t], j): the rows A(I, :) written transposed (n x k), j
+// fastest so the writes are contiguous; indices outside [0, nrows) give zeros.
+template <typename TS>
+__global__ void gather_rows_t_kernel(int64_t k, int64_t n, const TS* A, int64_t lda, int64_t nrows,
+                                     const int64_t* I, double* Rt, int64_t ldr) {
+  const int64_t total = k * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j, t;
+    split_index(e, n, j, t);
+    const int64_t i = I[t];
+    Rt[j + t * ldr] = (i >= 0 && i < nrows) ? load_as_double<TS>(A, i + j * lda) : 0.0;
+  }
+}
+
 __global__ void transpose_kernel(int64_t rows, int64_t cols, const double* X, int64_t ldx,
                                  double* Y, int64_t ldy) {
   __shared__ double tile[32][33];
@@ -615,6 +630,21 @@ int gather_rows(rpid_ctx ctx, int64_t k, int64_t n, const TS* A, int64_t lda, in
   RPID_HIP_CHECK(hipGetLastError());
   return RPID_OK;
 }
+
+template <typename TS>
+int gather_rows_t(rpid_ctx ctx, int64_t k, int64_t n, const TS* A, int64_t lda, int64_t nrows,
+                  const int64_t* I, double* Rt, int64_t ldr) {
+  hipLaunchKernelGGL((gather_rows_t_kernel<TS>), dim3(grid_for(k * n)), dim3(256), 0, ctx->stream, k, n, A,
+                     lda, nrows, I, Rt, ldr);
+  RPID_HIP_CHECK(hipGetLastError());
+  return RPID_OK;
+}
+template int gather_rows_t<double>(rpid_ctx, int64_t, int64_t, const double*, int64_t, int64_t,
+                                   const int64_t*, double*, int64_t);
+template int gather_rows_t<float>(rpid_ctx, int64_t, int64_t, const float*, int64_t, int64_t,
+                                  const int64_t*, double*, int64_t);
+template int gather_rows_t<uint16_t>(rpid_ctx, int64_t, int64_t, const uint16_t*, int64_t, int64_t,
+                                     const int64_t*, double*, int64_t);
 
 int transpose_f64(rpid_ctx ctx, int64_t rows, int64_t cols, const double* X, int64_t ldx,
                   double* Y, int64_t ldy) {
