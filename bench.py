@@ -451,6 +451,28 @@ def calibration_copy(torch, reps=5):
     return 2.0 * CALIB_MIB * (1 << 20) / (best * 1e-3)
 
 
+def cold_sketch(torch, R, ctx, A, Om, reps=10):
+    """The sketch call alone with the last-level cache flushed before each
+    call (a 512 MiB buffer written and synchronised outside the events):
+    (p10, p50, p90) ms."""
+    import numpy as np
+
+    flush = torch.empty(CALIB_MIB * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    out = []
+    for i in range(reps + 1):
+        flush.fill_(float(i))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        R.rpid_sketch(ctx, A, Om)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        if i > 0:
+            out.append(e0.elapsed_time(e1))
+    del flush
+    return [float(np.percentile(out, q)) for q in (10, 50, 90)]
+
+
 def cold_steps(torch, R, ctx, A, Om, steps):
     """The sequential step with the last-level cache flushed before each
     step: a 512 MiB buffer is written between steps, outside the events
@@ -462,6 +484,7 @@ def cold_steps(torch, R, ctx, A, Om, steps):
     out = []
     for i in range(steps + 1):
         flush.fill_(float(i))
+        torch.cuda.synchronize()  # the flush is done before the step starts
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(ctx.stream)
         X = R.rpid_sketch(ctx, A, Om)
@@ -887,6 +910,7 @@ def main():
     step_ms = main_r["ms_per_step"] if args.no_overlap else ov_ms
     cold = cold_steps(torch, R, ctx, *data[args.mode], args.cold_steps) if args.cold_steps > 0 else None
     sk_loop_ms = sketch_loop(torch, R, ctx, *data[args.mode])
+    sk_cold = {m: cold_sketch(torch, R, ctx, *data[m]) for m in order}
 
     # The call with the largest time per step and its one dominant kernel:
     # the sketch GEMM, the LUPP panel kernel (select_columns), or the
@@ -958,6 +982,8 @@ def main():
         "hbm_measured_GBps": hbm_measured / 1e9,
         "sketch_mfma_util": sketch_mfma,
         "sketch_ms_back_to_back": sk_loop_ms,
+        "sketch_ms_cold_p10_p50_p90": sk_cold,
+        "sketch_mfma_util_cold": {m: 2.0 * L * M * N / (v[1] * 1e-3) / PEAK_MFMA[m] for m, v in sk_cold.items()},
         "modes": {m: {"decomps_per_s": 1e3 / ov[m][0], "ms_per_step_overlapped": ov[m][0],
                       "ms_per_step_sequential": r["ms_per_step"],
                       "step_ms_p10_p50_p90": r["step_ms_p10_p50_p90"],
