@@ -84,6 +84,104 @@ __device__ __forceinline__ float scaled_or_nan(float v, int e) {
 constexpr int QC_NT = 512;
 constexpr int QC_G = 32;
 
+// Round-to-nearest-even to at most 3 significant mantissa bits reads only
+// the sign, the exponent, the top 4 mantissa bits and whether any lower bit
+// is set (E4M3 normals keep 3 bits, its subnormals fewer).  keep5 keeps
+// those bits of a float, the last one in bit 18 (the top 4 bits rounded to
+// odd at 5): the result rounds to the same code as the float at every
+// power-of-two scale that keeps FP32 subnormal inputs away from the nonzero
+// codes (scale exponents up to 116), infinities stay infinite and NaN stays
+// NaN.  Two such floats share one register: one in bits 18..31, the other
+// shifted down into bits 0..13.
+__device__ __forceinline__ uint32_t keep5(uint32_t b) {
+  return (b | ((b & 0x3FFFFu) + 0x3FFFFu)) & 0xFFFC0000u;
+}
+
+__device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  uint32_t r = red[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = max(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// Columns of whole groups of 4 QC_NT rows (at most 4 QC_NT QC_G), 16-byte
+// aligned: the same quantisation with one 16-byte load per group and thread,
+// QC_WIN of them in flight at a time, and the column kept as keep5 fields,
+// two to a register (64 registers per thread instead of 128), so that two
+// workgroups share a CU and one's loads overlap the other's reduction and
+// stores.  The largest |A(i, j)| comes from an integer maximum of the bit
+// patterns without sign, which also tells a non-finite entry (the patterns
+// from 0x7F800000 up).  A column with a non-finite entry, or scaled by more
+// than 2^116 (largest entry below about 2^-108), is quantised again from A
+// itself.
+constexpr int QC_WIN = 12;
+constexpr int QC_BUF_WORD3 = 0x00020000;  // raw 32-bit loads, out-of-range reads give 0
+constexpr int QC_KEEP5_MAX_EXP = 116;
+
+__global__ __launch_bounds__(QC_NT) __attribute__((amdgpu_waves_per_eu(4)))
+void quantize_cols_v4_kernel(const float* A, int64_t m, int64_t lda, uint8_t* Aq, int64_t ldq, int* ea) {
+  __shared__ uint32_t red[QC_NT / 64];
+  const int64_t j = blockIdx.x;
+  const int64_t t = threadIdx.x;
+  const int ng = (int)(m / (4 * QC_NT));
+  const float* col = A + j * lda;
+  // buffer loads over the column's m rows: one offset register per thread,
+  // the group's offset a scalar, and groups past the column read zeros
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(col), (short)0, (int)(4 * m), QC_BUF_WORD3);
+  auto load = [&](int g) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(16 * t), 16 * QC_NT * g, 0);
+    return make_uint4(v[0], v[1], v[2], v[3]);
+  };
+  uint4 q[QC_WIN];
+#pragma unroll
+  for (int g = 0; g < QC_WIN; ++g) q[g] = load(g);
+  uint32_t h[QC_G][2];
+  uint32_t mx = 0u;
+#pragma unroll
+  for (int g = 0; g < QC_G; ++g) {
+    uint4 x = q[g % QC_WIN];
+    if (g + QC_WIN < QC_G) q[g % QC_WIN] = load(g + QC_WIN);
+    mx = max(mx, max(max(x.x & 0x7FFFFFFFu, x.y & 0x7FFFFFFFu), max(x.z & 0x7FFFFFFFu, x.w & 0x7FFFFFFFu)));
+    h[g][0] = keep5(x.y) | (keep5(x.x) >> 18);
+    h[g][1] = keep5(x.w) | (keep5(x.z) >> 18);
+    // pin the packing here (an empty asm that reads and writes the pair):
+    // sunk to the stores, it would keep the 128 loaded values alive instead
+    asm volatile("" : "+v"(h[g][0]), "+v"(h[g][1]));
+  }
+  mx = block_max_u32(mx, red);
+  const bool cnf_any = mx >= 0x7F800000u;
+  const int ce = cnf_any ? 0 : scale_exp(__uint_as_float(mx));
+  if (t == 0) ea[j] = ce;
+  uint8_t* cq = Aq + j * ldq;
+  if (!cnf_any && ce <= QC_KEEP5_MAX_EXP) {
+    // every scaled value lies within +-448: the hardware conversion applies
+#pragma unroll
+    for (int g = 0; g < QC_G; ++g)
+      if (g < ng) {
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(__uint_as_float(h[g][0] << 18), ce),
+                                                ldexpf(__uint_as_float(h[g][0] & 0xFFFC0000u), ce), 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(__uint_as_float(h[g][1] << 18), ce),
+                                            ldexpf(__uint_as_float(h[g][1] & 0xFFFC0000u), ce), w, true);
+        *reinterpret_cast<int*>(cq + 4 * QC_NT * g + 4 * t) = w;
+      }
+  } else {
+    // a non-finite entry (scale 1, NaN codes for NaN and infinities) or a
+    // column of tiny values: quantise again from A itself
+#pragma unroll 1
+    for (int g = 0; g < ng; ++g) {
+      const float4 x = *reinterpret_cast<const float4*>(col + 4 * QC_NT * g + 4 * t);
+      *reinterpret_cast<uint32_t*>(cq + 4 * QC_NT * g + 4 * t) =
+          e4m3_pack4(scaled_or_nan(x.x, ce), scaled_or_nan(x.y, ce), scaled_or_nan(x.z, ce), scaled_or_nan(x.w, ce));
+    }
+  }
+}
+
 __global__ __launch_bounds__(QC_NT) void quantize_cols_kernel(const float* A, int64_t m, int64_t lda,
                                                               uint8_t* Aq, int64_t ldq, int* ea) {
   __shared__ float red[QC_NT / 64];
@@ -296,8 +394,13 @@ int sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, 
     RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Aq), (size_t)mq * n / 8, 0ull));
     RPID_CHECK(launch_fill_u64(ctx, reinterpret_cast<uint64_t*>(Pq), (size_t)mq * l / 8, 0ull));
   }
-  hipLaunchKernelGGL(quantize_cols_kernel, dim3((unsigned)n), dim3(QC_NT), 0, ctx->stream, A, m, lda,
-                     Aq, mq, ea);
+  if (reinterpret_cast<uintptr_t>(A) % 16 == 0 && lda % 4 == 0 && m % (4 * QC_NT) == 0 &&
+      m <= (int64_t)QC_G * 4 * QC_NT)
+    hipLaunchKernelGGL(quantize_cols_v4_kernel, dim3((unsigned)n), dim3(QC_NT), 0, ctx->stream, A, m, lda,
+                       Aq, mq, ea);
+  else
+    hipLaunchKernelGGL(quantize_cols_kernel, dim3((unsigned)n), dim3(QC_NT), 0, ctx->stream, A, m, lda,
+                       Aq, mq, ea);
   RPID_HIP_CHECK(hipGetLastError());
   // at least eight columns of Omega per workgroup (two rounds of its four waves)
   const int parts = (int)std::min<int64_t>(OMAX_PARTS, (m + 7) / 8);

@@ -231,6 +231,43 @@ def test_fp8_codes_ties_and_subnormals_exact(R, ctx, m, l):
     assert np.array_equal(X, O.sketch_fp8(A, Om))
 
 
+@pytest.mark.parametrize("m,n,l", [(4096, 48, 300), (65536, 8, 300)])
+def test_fp8_codes_scaled_columns_exact(R, ctx, m, n, l):
+    """The E4M3 codes exactly at row counts that are whole multiples of 2048
+    (16-byte loads, the column kept as sign, exponent, top 4 mantissa bits
+    and a sticky bit), over per-column scales from 2^30 down to 2^-150:
+    column j is a column of midpoints of consecutive codes (ties), exact
+    codes and arbitrary values, times 2^-s_j, with 448 2^-s_j in row 0 (so
+    its scale exponent is s_j) and FP32 subnormals in rows 1..6 (scaled
+    down with the column past s_j = 116, so that row 0 stays largest).  Scale
+    exponents above 116 take the exact re-read of the column, and the
+    subnormals must land on the same codes as in the oracle's FP64
+    arithmetic at every scale."""
+    rng = np.random.default_rng(17)
+    table = O.e4m3_values()
+    k = rng.integers(0, table.size - 1, size=(m, n))
+    mids = (table[k] + table[k + 1]) / 2.0
+    kind = rng.integers(0, 3, size=(m, n))  # 0: midpoint, 1: exact value, 2: arbitrary
+    base = np.where(kind == 0, mids, np.where(kind == 1, table[k], rng.uniform(0.0, 448.0, (m, n))))
+    base = base * np.where(rng.random((m, n)) < 0.5, -1.0, 1.0)
+    base[0, :] = 448.0
+    s = np.round(np.linspace(-30, 150, n)).astype(int)
+    if n >= 8:
+        s[1:4] = [116, 117, 120]
+    A = base * np.ldexp(1.0, -s)[None, :]
+    tiny = np.array([2.0**-127, -(2.0**-130), 3 * 2.0**-149, 2.0**-149, -1.5 * 2.0**-127, 2.0**-140])
+    A[1:7, :] = tiny[:, None] * np.ldexp(1.0, -np.maximum(s - 116, 0))[None, :]
+    A = A.astype(np.float32).astype(np.float64)
+    assert all(O.fp8_scale_exp(np.abs(A[:, j]).max()) == s[j] for j in range(n))
+    rows = np.concatenate([np.arange(7), np.sort(rng.choice(np.arange(7, m), l - 7, replace=False))])
+    Om = np.zeros((l, m))
+    Om[np.arange(l), rows] = 1.0
+    say("fp8 codes scaled", m, n, l)
+    X = host(R.rpid_sketch_fp8(ctx, inputs.torch_colmajor(A, torch.float32, "cuda"),
+                               inputs.torch_colmajor(Om, torch.float32, "cuda")))
+    assert np.array_equal(X, O.sketch_fp8(A, Om))
+
+
 def test_lupp_grid_above_one_workgroup_per_cu_refused(R, ctx):
     """A panel that would need more workgroups than compute units (FP64, k =
     384, 65536 rows: 128 rows per workgroup at most) is refused on the host
