@@ -11,6 +11,7 @@ GPU is absent, the calls raise.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import torch
@@ -159,6 +160,9 @@ class Context:
         self.handle = h
 
     def close(self):
+        worker = self.__dict__.pop("_side_worker", None)
+        if worker is not None:
+            worker.stop()
         if self.handle:
             lib().rpid_destroy(self.handle)
             self.handle = None
@@ -501,19 +505,72 @@ def rpid_mlp_loss(ctx, yhat, target, tau):
     return loss, dy
 
 
+class _SideWorker:
+    """One thread that runs the side branch of decompose_overlapped, started
+    once per side context and woken per step, so that no thread start sits
+    between the column pivots and the CUR step's first launches."""
+
+    def __init__(self):
+        import threading
+
+        self._go = threading.Event()
+        self._done = threading.Event()
+        self._job = None
+        self._out = None
+        self._thread = threading.Thread(target=self._loop, daemon=True)
+        self._thread.start()
+
+    def _loop(self):
+        while True:
+            self._go.wait()
+            self._go.clear()
+            job = self._job
+            if job is None:
+                return
+            try:
+                self._out = (job(), None)
+            except Exception as e:  # noqa: BLE001 (re-raised in the caller's thread)
+                self._out = (None, e)
+            self._done.set()
+
+    def start(self, job):
+        self._job = job
+        self._done.clear()
+        self._go.set()
+
+    def result(self):
+        self._done.wait()
+        out, err = self._out
+        self._out = None
+        if err is not None:
+            raise err
+        return out
+
+    def stop(self):
+        self._job = None
+        self._go.set()
+        self._thread.join(timeout=5.0)
+
+
+def _relative(sums: torch.Tensor) -> float:
+    """||A - PQ||_F / ||A||_F from the device pair [||A - PQ||^2, ||A||^2]
+    (the same expression the library evaluates for rpid_residual)."""
+    d, a = sums.cpu().tolist()
+    return math.sqrt(d / a) if a > 0.0 else 0.0
+
+
 def decompose_overlapped(ctx, ctx2, A, Omega, k, refine_steps=None):
     """Alg. 2 end to end with both residuals, the two branches that follow
     the column pivots run concurrently: Z and the ID residual on ctx2's
-    stream (enqueued from a worker thread; the library calls release the
-    interpreter lock), the CUR step and its residual on ctx's stream.  The
-    worker starts after the CUR step's first launches are on their way, so
-    the CUR step's cooperative LUPP launch finds the compute units free (the
-    order that measured fastest).  ctx2 needs its own stream; the two contexts
-    have separate workspaces, so the branches share nothing but their
-    read-only inputs.  The results are those of the sequential order (the
-    same kernels on the same inputs)."""
-    import threading
-
+    stream (enqueued by a worker thread that ctx2 keeps; the library calls
+    release the interpreter lock), the CUR step and its residual on ctx's
+    stream.  The CUR call is made as soon as the worker is woken, so its
+    cooperative row LUPP launch finds the compute units free (the order that
+    measured fastest); both residuals are left on the device
+    (rpid_residual_sums) and read once at the end.  ctx2 needs its own
+    stream; the two contexts have separate workspaces, so the branches share
+    nothing but their read-only inputs.  The results are those of the
+    sequential order (the same kernels on the same inputs)."""
     X = rpid_sketch(ctx, A, Omega)
     if refine_steps is None:
         refine_steps = 0 if X.dtype == torch.float64 else 1
@@ -521,29 +578,27 @@ def decompose_overlapped(ctx, ctx2, A, Omega, k, refine_steps=None):
     out = dict(X=X, J=J, Lf=Lf, Uf=Uf, diag=diag, k_eff=keff, status=st)
     if st != 0:
         return out
+    worker = ctx2.__dict__.get("_side_worker")
+    if worker is None:
+        worker = ctx2._side_worker = _SideWorker()
     ready = torch.cuda.Event()
     ready.record(ctx.stream)
-    side = {}
 
     def id_branch():
-        try:
-            ctx2.stream.wait_event(ready)
-            Z, _ = rpid_id_coeffs(ctx2, X, k, J, Lf, Uf, refine_steps=refine_steps)
-            side["Z"] = Z
-            side["rid"] = rpid_residual(ctx2, RESIDUAL_ID, A, k, J, Z=Z)
-        except Exception as e:  # noqa: BLE001 (re-raised in the caller's thread)
-            side["error"] = e
+        ctx2.stream.wait_event(ready)
+        Z, _ = rpid_id_coeffs(ctx2, X, k, J, Lf, Uf, refine_steps=refine_steps)
+        return Z, rpid_residual_sums(ctx2, RESIDUAL_ID, A, k, J, Z=Z)
 
-    worker = threading.Thread(target=id_branch)
-    worker.start()
+    worker.start(id_branch)
     try:
         I, U, keff_i, st_i = rpid_cur(ctx, A, k, J)
-        rcur = rpid_residual(ctx, RESIDUAL_CUR, A, k, J, I=I, U=U) if st_i == 0 else None
+        scur = rpid_residual_sums(ctx, RESIDUAL_CUR, A, k, J, I=I, U=U) if st_i == 0 else None
     finally:
-        worker.join()
-    if "error" in side:
-        raise side["error"]
-    out.update(Z=side["Z"], I=I, U=U, status_I=st_i, residual_id=side["rid"], residual_cur=rcur)
+        Z, sid = worker.result()
+    ctx2.stream.synchronize()
+    ctx.stream.synchronize()
+    out.update(Z=Z, I=I, U=U, status_I=st_i, residual_id=_relative(sid),
+               residual_cur=_relative(scur) if scur is not None else None)
     return out
 
 

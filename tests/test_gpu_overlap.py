@@ -36,10 +36,13 @@ def test_overlapped_equals_sequential(dt):
             assert torch.equal(ov["J"], seq["J"]) and torch.equal(ov["I"], seq["I"])
             assert torch.equal(ov["Z"], seq["Z"]) and torch.equal(ov["U"], seq["U"])
             assert ov["residual_id"] == rid and ov["residual_cur"] == rcur
+        worker = ctx2.__dict__.get("_side_worker")
     finally:
         ctx2.close()
         ctx.close()
     assert np.isfinite(rid) and np.isfinite(rcur)
+    # the side context's worker thread ends with the context
+    assert worker is not None and not worker._thread.is_alive()
 
 
 def test_residual_sums_match_residual():
