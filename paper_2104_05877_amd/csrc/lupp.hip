@@ -193,18 +193,32 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
   // modulus, the smallest row on ties), by a pairwise tree: a pair keeps its
   // right (larger-row) entry only if that entry is strictly larger
   auto local_candidate = [&]() {
-    T av[R], sv[R];
-    int iv[R];
+    // runs of LC consecutive rows are scanned in order (a later row replaces
+    // the run's best only if strictly larger), then the run winners go
+    // through the pairwise tree: the same first-largest row as a tree over
+    // all R rows, with 3 R / LC instead of 3 R values live at once
+    constexpr int LC = R >= 64 ? 8 : 1;
+    constexpr int NCH = R / LC;
+    T av[NCH], sv[NCH];
+    int iv[NCH];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      av[q] = fabs(s[q]);
-      sv[q] = s[q];
-      iv[q] = q;
+    for (int c = 0; c < NCH; ++c) {
+      av[c] = fabs(s[c * LC]);
+      sv[c] = s[c * LC];
+      iv[c] = c * LC;
+#pragma unroll
+      for (int u = 1; u < LC; ++u) {
+        const T x = fabs(s[c * LC + u]);
+        const bool right = x > av[c];
+        av[c] = right ? x : av[c];
+        sv[c] = right ? s[c * LC + u] : sv[c];
+        iv[c] = right ? c * LC + u : iv[c];
+      }
     }
 #pragma unroll
-    for (int w = 1; w < R; w *= 2) {
+    for (int w = 1; w < NCH; w *= 2) {
 #pragma unroll
-      for (int q = 0; q + w < R; q += 2 * w) {
+      for (int q = 0; q + w < NCH; q += 2 * w) {
         const bool right = av[q + w] > av[q];
         av[q] = right ? av[q + w] : av[q];
         sv[q] = right ? sv[q + w] : sv[q];
@@ -295,15 +309,14 @@ __global__ __launch_bounds__(NTMAX) void lupp_panel_kernel(LuppArgs<T> a) {
         // every round requests all PMAX words of the lane (indices past G
         // read word G-1 and are ignored): a fixed number of loads per round,
         // so the second round can stay in flight while the first is checked
-        const uint64_t* xw[PMAX];
-#pragma unroll
-        for (int c = 0; c < PMAX; ++c)
-          xw[c] = &a.xval[(g % kValRep) * a.xrep + ((int64_t)par * G + min(lane + 64 * c, G - 1)) * W];
+        // the lane's words, addressed afresh per round (no pointer array kept
+        // live beside the panel registers)
+        const uint64_t* xw0 = &a.xval[(g % kValRep) * a.xrep + (int64_t)par * G * W];
         auto request = [&](uint64_t(&w)[W * PMAX]) {
 #pragma unroll
           for (int c = 0; c < PMAX; ++c)
 #pragma unroll
-            for (int e = 0; e < W; ++e) w[c * W + e] = wload(xw[c] + e);
+            for (int e = 0; e < W; ++e) w[c * W + e] = wload(xw0 + min(lane + 64 * c, G - 1) * W + e);
         };
         // accept the words of a set that carry this step's tag
         auto accept = [&](const uint64_t(&w)[W * PMAX], unsigned asked) {

@@ -198,8 +198,9 @@ int tri_solve(rpid_ctx ctx, int64_t k, int64_t nrhs, const double* T, int64_t ld
 int tri_inverse(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, bool lower, bool unit,
                 double* W, int64_t ldw, size_t ws_tmp);
 
-// Register-resident triangular kernels (sweep.hip), k <= 288; the scratch
-// region at ws_tmp must hold sweep_scratch_bytes(k).
+// Register-resident triangular kernels (sweep.hip), k <= 512 (one launch up
+// to 160, one 2 x 2 split up to 288, repeated splits of a leading block of 128
+// above); the scratch region at ws_tmp must hold sweep_scratch_bytes(k).
 bool sweep_supported(int64_t k);
 size_t sweep_scratch_bytes(int64_t k);
 // For `batch` (1 or 2) SPD k x k matrices G_b (stride apart, lower part

@@ -431,13 +431,60 @@ SweepJob make_job(int k, const double* in, int64_t ldi, int in_upper, double* ou
 }
 
 // One launch holds a matrix of order <= 160 in registers; up to 288 the
-// matrix is split once into 2 x 2 blocks (leading block 128).
+// matrix is split once into 2 x 2 blocks (leading block 128); up to 512 the
+// leading block of 128 is split off and the trailing block, of order k - 128,
+// is treated the same way (recursively).
 constexpr int64_t SW_ONE = 160;
 constexpr int64_t SW_SPLIT = 128;
+constexpr int64_t SW_MAX = 512;
+
+// Cholesky G = R^T R and Winv = R^{-1} (upper) for one SPD matrix of any
+// order up to SW_MAX by repeated splitting:
+//   R11^T R11 = G11 (one sweep, W11 = R11^{-1}), R12 = W11^T G12,
+//   S = G22 - R12^T R12 formed explicitly, R22 and W22 from S (the same
+//   function), W12 = -W11 R12 W22, W21 = 0.
+// A non-positive pivot at global column c writes c + 1 to *status (c counts
+// from the first column of the outermost call: status_add); *status = 0 is
+// written on success only by the outermost call (write_ok).
+int chol_inverse_split(rpid_ctx ctx, int64_t k, const double* G, int64_t ldg, double* Winv,
+                       int64_t ldw, int64_t* status, int status_add, bool write_ok,
+                       size_t ws_tmp) {
+  SweepArgs a{};
+  a.chol = 1;
+  a.unit = 0;
+  const int64_t k1 = k <= SW_ONE ? k : SW_SPLIT, k2 = k - k1;
+  a.job[0] = make_job((int)k1, G, ldg, 0, Winv, ldw, 1);
+  a.job[0].status = status;
+  a.job[0].status_add = status_add;
+  a.job[0].status_ok = write_ok ? 1 : 0;
+  RPID_CHECK(dispatch_sweep(ctx, a, 1));
+  if (k2 == 0) return RPID_OK;
+  Carve cv;
+  cv.off = ws_tmp;
+  const size_t o_R12 = cv.take<double>((size_t)k1 * k2);
+  const size_t o_S = cv.take<double>((size_t)k2 * k2);
+  const size_t o_T = cv.take<double>((size_t)k1 * k2);
+  const size_t ws_next = cv.off;
+  RPID_CHECK(ws_check(ctx, cv.off));
+  double* R12 = ws_ptr<double>(ctx, o_R12);
+  double* S = ws_ptr<double>(ctx, o_S);
+  double* T = ws_ptr<double>(ctx, o_T);
+  double* W22 = Winv + k1 + k1 * ldw;
+  RPID_CHECK(dgemm(ctx, true, false, k1, k2, k1, 1.0, Winv, ldw, G + k1 * ldg, ldg, 0.0, R12, k1,
+                   ws_next));
+  RPID_CHECK(convert_matrix<double, double>(ctx, k2, k2, G + k1 + k1 * ldg, ldg, S, k2));
+  RPID_CHECK(dgemm(ctx, true, false, k2, k2, k1, -1.0, R12, k1, R12, k1, 1.0, S, k2, ws_next));
+  RPID_CHECK(chol_inverse_split(ctx, k2, S, k2, W22, ldw, status, status_add + (int)k1, false,
+                                ws_next));
+  RPID_CHECK(dgemm(ctx, false, false, k1, k2, k2, 1.0, R12, k1, W22, ldw, 0.0, T, k1, ws_next));
+  RPID_CHECK(dgemm(ctx, false, false, k1, k2, k1, -1.0, Winv, ldw, T, k1, 0.0, Winv + k1 * ldw, ldw,
+                   ws_next));
+  return zero_blocks(ctx, 1, Winv + k1, nullptr, ldw, k2, k1);
+}
 
 }  // namespace
 
-bool sweep_supported(int64_t k) { return k >= 1 && k <= SW_SPLIT + SW_ONE; }
+bool sweep_supported(int64_t k) { return k >= 1 && k <= SW_MAX; }
 
 size_t sweep_scratch_bytes(int64_t k) {
   // R12, P, T for two matrices, then room for the GEMM partial sums
@@ -448,6 +495,10 @@ int chol_inverse_batched(rpid_ctx ctx, int batch, int64_t k, const double* G, in
                          int64_t stride, double* Winv, int64_t ldw, int64_t wstride,
                          int64_t* status_dev, size_t ws_tmp) {
   if (!sweep_supported(k) || batch < 1 || batch > 2) return RPID_ERR_UNSUPPORTED;
+  if (k > SW_SPLIT + SW_ONE) {
+    if (batch != 1) return RPID_ERR_UNSUPPORTED;
+    return chol_inverse_split(ctx, k, G, ldg, Winv, ldw, status_dev, 0, true, ws_tmp);
+  }
   SweepArgs a{};
   a.chol = 1;
   a.unit = 0;
@@ -519,7 +570,9 @@ int tri_inverse_sweep(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, boo
     a.job[0] = make_job((int)k, T, ldt, up, W, ldw, up);
     return dispatch_sweep(ctx, a, 1);
   }
-  // both diagonal blocks in one launch, then the off-diagonal block:
+  // both diagonal blocks (in one launch while the trailing one fits a
+  // sweep; above that the trailing block by this function), then the
+  // off-diagonal block:
   //   lower: W21 = -W22 T21 W11;  upper: W12 = -W11 T12 W22
   const int64_t k1 = SW_SPLIT, k2 = k - SW_SPLIT;
   Carve cv;
@@ -529,8 +582,14 @@ int tri_inverse_sweep(rpid_ctx ctx, int64_t k, const double* T, int64_t ldt, boo
   RPID_CHECK(ws_check(ctx, cv.off));
   double* Y = ws_ptr<double>(ctx, o_Y);
   a.job[0] = make_job((int)k1, T, ldt, up, W, ldw, up);
-  a.job[1] = make_job((int)k2, T + k1 + k1 * ldt, ldt, up, W + k1 + k1 * ldw, ldw, up);
-  RPID_CHECK(dispatch_sweep(ctx, a, 2));
+  if (k2 <= SW_ONE) {
+    a.job[1] = make_job((int)k2, T + k1 + k1 * ldt, ldt, up, W + k1 + k1 * ldw, ldw, up);
+    RPID_CHECK(dispatch_sweep(ctx, a, 2));
+  } else {
+    RPID_CHECK(dispatch_sweep(ctx, a, 1));
+    RPID_CHECK(tri_inverse_sweep(ctx, k2, T + k1 + k1 * ldt, ldt, lower, unit, W + k1 + k1 * ldw, ldw,
+                                 ws_dg));
+  }
   const double* W11 = W;
   const double* W22 = W + k1 + k1 * ldw;
   if (lower) {

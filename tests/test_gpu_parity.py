@@ -238,11 +238,14 @@ def test_exp1000x800_f64_end_to_end(R, ctx):
 
 
 @pytest.mark.parametrize("m,n,k,l,seed", [(2048, 1800, 256, 272, 5), (1500, 1700, 200, 200, 6),
-                                          (1300, 1100, 170, 180, 7)])
+                                          (1300, 1100, 170, 180, 7), (2600, 2400, 400, 420, 8),
+                                          (3000, 2600, 512, 544, 9)])
 def test_large_k_f64_end_to_end(R, ctx, m, n, k, l, seed):
     """k above what one workgroup holds in registers (the triangular factors
-    are split into 2 x 2 blocks), k not a multiple of 32: J and I bit-exact,
-    Z within its conditioning, U through the CUR residual (1e-9 relative)."""
+    are split into 2 x 2 blocks up to 288, and a leading block of 128 is split
+    off repeatedly above that: 400 and 512), k not a multiple of 32: J and I
+    bit-exact, Z within its conditioning, U through the CUR residual (1e-9
+    relative)."""
     say("large-k f64", m, n, k, l)
     A, Om = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 1.0), seed)
     o = O.decompose(A, Om, k, gaps=True)
