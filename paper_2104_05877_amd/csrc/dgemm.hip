@@ -134,7 +134,16 @@ __global__ void dgemm_reduce_kernel(const double* part, int splits, int64_t stri
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e % M, j = e / M;
     double s = 0.0;
-    for (int t = 0; t < splits; ++t) s += part[(int64_t)t * stride + e];
+    // eight loads in flight per round, added in the same order as one by one
+    int t = 0;
+    for (; t + 8 <= splits; t += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(t + u) * stride + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; t < splits; ++t) s += part[(int64_t)t * stride + e];
     double* c = &C[i + j * ldc];
     *c = alpha * s + (beta == 0.0 ? 0.0 : beta * *c);
   }

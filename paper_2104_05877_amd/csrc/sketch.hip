@@ -743,8 +743,18 @@ __global__ void split_reduce_kernel(const TA* part, int split, int64_t stride, i
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e % l, j = e / l;
-    TA s = part[r + j * ldp];
-    for (int t = 1; t < split; ++t) s += part[(int64_t)t * stride + r + j * ldp];
+    const int64_t o = r + j * ldp;
+    TA s = part[o];
+    // eight loads in flight per round, added in the same order as one by one
+    int t = 1;
+    for (; t + 8 <= split; t += 8) {
+      TA v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(t + u) * stride + o];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; t < split; ++t) s += part[(int64_t)t * stride + o];
     X[r + j * ldx] = (TX)s;
   }
 }
