@@ -210,6 +210,28 @@ int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, 
                         int64_t ldu, void* diagU, int64_t* k_eff);
 
 /*
+ * S3 without a host read: rpid_select_columns (same pivots, same outputs)
+ * with its status written to a device word in stream order, so that the work
+ * that depends on J can be enqueued before the pivots are known.
+ *   X .. diagU   as for rpid_select_columns
+ *   status_dev   DEVICE int64*, caller-owned: receives 0 (k pivots), t + 1
+ *                for an exactly zero pivot at 0-based step t (the first t
+ *                pivots are defined), or a negative RPID_ERR_* code
+ *                (RPID_ERR_NONFINITE for NaN/Inf in X, RPID_ERR_TIMEOUT if
+ *                the pivot exchange gave up)
+ * Returns RPID_OK once the work is enqueued, a negative argument index
+ * (-14 for a NULL status_dev), or a launch error; it never synchronises.
+ * When the status is not 0 the entries of J past the defined pivots are left
+ * as they were.  Every call of this library that takes J or I treats entries
+ * outside [0, n) (resp. [0, m)) as absent, reading zeros and writing
+ * nothing, so work enqueued on such J computes garbage but never accesses
+ * memory out of bounds; the caller discards it after reading the status.
+ */
+int rpid_select_columns_async(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                              int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
+                              int64_t ldu, void* diagU, int64_t* status_dev);
+
+/*
  * Sparse sign embedding (Sec. 2.2, third embedding): Gamma (l x m) has in
  * column i the entries signs[i, s] (+-1) at rows rows[i, s], s < zeta, times
  * `scale`; X = Gamma A for a dense A.  The draws are the caller's:

@@ -694,7 +694,8 @@ __global__ void scatter_cols_f64_kernel(int64_t k, const double* P, const int64_
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e % k, t = e / k;
-    U[r + J[t] * ldu] = P[e];
+    const int64_t j = J[t];
+    if (j >= 0 && j < k) U[r + j * ldu] = P[e];
   }
 }
 
@@ -929,9 +930,12 @@ int rpid_cur_sketch(rpid_ctx ctx, const void* A, rpid_dtype a_t, int64_t m, int6
 }
 
 // ---------------------------------------------------------------------------
-int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
-                        int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
-                        int64_t ldu, void* diagU, int64_t* k_eff) {
+// The column LUPP of rpid_select_columns and rpid_select_columns_async: the
+// status goes to status_ext (a caller's device word) when given, else to the
+// workspace, from where it is read back only if k_eff is given.
+static int select_columns_impl(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                               int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
+                               int64_t ldu, void* diagU, int64_t* k_eff, int64_t* status_ext) {
   if (!ctx) return -1;
   if (!X) return -2;
   if (!is_lupp_type(x_t)) return -3;
@@ -950,7 +954,7 @@ int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, 
   const size_t o_status = cv.take<int64_t>(8);
   const size_t o_lupp = cv.off;
   RPID_CHECK(ensure_workspace(ctx, o_lupp + lupp_workspace_bytes(ctx, n, k, es)));
-  int64_t* status_dev = ws_ptr<int64_t>(ctx, o_status);
+  int64_t* status_dev = status_ext ? status_ext : ws_ptr<int64_t>(ctx, o_status);
   // Xᵀ panel: P(i, j) = X[j + i * ldx]
   int s;
   if (x_t == RPID_F64)
@@ -966,6 +970,20 @@ int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, 
   if (st < 0) return (int)st;
   *k_eff = (st == 0) ? k : st - 1;
   return (int)st;
+}
+
+int rpid_select_columns(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                        int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
+                        int64_t ldu, void* diagU, int64_t* k_eff) {
+  return select_columns_impl(ctx, X, x_t, l, n, ldx, k, J, Lf, ldl, Uf, ldu, diagU, k_eff, nullptr);
+}
+
+int rpid_select_columns_async(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64_t n,
+                              int64_t ldx, int64_t k, int64_t* J, void* Lf, int64_t ldl, void* Uf,
+                              int64_t ldu, void* diagU, int64_t* status_dev) {
+  if (!status_dev) return -14;
+  return select_columns_impl(ctx, X, x_t, l, n, ldx, k, J, Lf, ldl, Uf, ldu, diagU, nullptr,
+                             status_dev);
 }
 
 // ---------------------------------------------------------------------------
@@ -1185,7 +1203,7 @@ int rpid_id_coeffs_cpqr(rpid_ctx ctx, rpid_dtype r_t, int64_t k, int64_t n, cons
   // Z = R11^{-1} R_top, with R11 = R_top(:, J) upper triangular in pivot order
   RPID_CHECK(tri_inverse(ctx, k, R11, k, false, false, Wi, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, false, k, n, k, 1.0, Wi, k, R64, ld64, 0.0, Z, ldz, o_tmp));
-  return set_identity_columns(ctx, k, J, Z, ldz);
+  return set_identity_columns(ctx, k, n, J, Z, ldz);
 }
 
 // ---------------------------------------------------------------------------
@@ -1254,7 +1272,7 @@ int rpid_id_coeffs_ls(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, in
   RPID_CHECK(dgemm(ctx, false, false, k, k, k, 1.0, W, k, W + kk, k, 0.0, Ri, k, o_tmp));
   RPID_CHECK(dgemm(ctx, true, false, k, n, l, 1.0, in, l, X64, ld64, 0.0, Y, k, o_tmp));
   RPID_CHECK(dgemm(ctx, false, false, k, n, k, 1.0, Ri, k, Y, k, 0.0, Z, ldz, o_tmp));
-  RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
+  RPID_CHECK(set_identity_columns(ctx, k, n, J, Z, ldz));
   int64_t st[2] = {0, 0};
   RPID_HIP_CHECK(hipMemcpyAsync(ctx->host_status, status_dev, 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -1318,7 +1336,7 @@ int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64
     ldl64 = n;
   }
   RPID_CHECK(dgemm(ctx, true, true, k, n, k, 1.0, Winv, k, L64, ldl64, 0.0, Z, ldz, o_tmp));
-  RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
+  RPID_CHECK(set_identity_columns(ctx, k, n, J, Z, ldz));
   if (refine_steps > 0) {
     double* U64 = ws_ptr<double>(ctx, o_U64);
     double* X1 = ws_ptr<double>(ctx, o_X1);
@@ -1343,7 +1361,7 @@ int rpid_id_coeffs(rpid_ctx ctx, const void* X, rpid_dtype x_t, int64_t l, int64
         RPID_CHECK(convert_matrix<float, double>(ctx, k, n, (const float*)X, ldx, res, k));
       RPID_CHECK(dgemm(ctx, false, false, k, n, k, -1.0, X1, k, Z, ldz, 1.0, res, k, o_tmp));
       RPID_CHECK(dgemm(ctx, true, false, k, n, k, 1.0, Pm, k, res, k, 1.0, Z, ldz, o_tmp));
-      RPID_CHECK(set_identity_columns(ctx, k, J, Z, ldz));
+      RPID_CHECK(set_identity_columns(ctx, k, n, J, Z, ldz));
     }
   }
   if (eta) {

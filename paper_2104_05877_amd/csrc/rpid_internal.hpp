@@ -251,7 +251,8 @@ int transpose_f64(rpid_ctx ctx, int64_t rows, int64_t cols, const double* X, int
 // c * sum_i S(i, i) (trace of a Gram matrix = ||C||_F^2).
 int add_trace_shift(rpid_ctx ctx, int64_t k, double* G, int64_t ldg, double c);
 // Set the columns J[t] of Z (k x n) to e_t.
-int set_identity_columns(rpid_ctx ctx, int64_t k, const int64_t* J, double* Z, int64_t ldz);
+// Z(:, J[t]) = e_t (entries of J outside [0, n) skipped).
+int set_identity_columns(rpid_ctx ctx, int64_t k, int64_t n, const int64_t* J, double* Z, int64_t ldz);
 // Split an FP64 matrix into `parts` BF16 terms: S = sum_p D_p (greedy RNE
 // residuals); D is rows x (parts * cols) with part p in columns [p cols, (p+1) cols).
 int split_bf16(rpid_ctx ctx, int64_t rows, int64_t cols, const double* S, int64_t lds, int parts,

@@ -129,13 +129,15 @@ __global__ void trace_shift_kernel(int64_t k, double* G, int64_t ldg, double c) 
   for (int64_t i = threadIdx.x; i < k; i += blockDim.x) G[i + i * ldg] += shift;
 }
 
-__global__ void identity_cols_kernel(int64_t k, const int64_t* J, double* Z, int64_t ldz) {
+// Z(:, J[t]) = e_t; entries of J outside [0, n) are skipped
+__global__ void identity_cols_kernel(int64_t k, int64_t n, const int64_t* J, double* Z, int64_t ldz) {
   const int64_t total = k * k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t c, t;
     split_index(e, k, c, t);
-    Z[c + J[t] * ldz] = (c == t) ? 1.0 : 0.0;
+    const int64_t j = J[t];
+    if (j >= 0 && j < n) Z[c + j * ldz] = (c == t) ? 1.0 : 0.0;
   }
 }
 
@@ -661,8 +663,8 @@ int add_trace_shift(rpid_ctx ctx, int64_t k, double* G, int64_t ldg, double c) {
   return RPID_OK;
 }
 
-int set_identity_columns(rpid_ctx ctx, int64_t k, const int64_t* J, double* Z, int64_t ldz) {
-  hipLaunchKernelGGL(identity_cols_kernel, dim3(grid_for(k * k)), dim3(256), 0, ctx->stream, k, J,
+int set_identity_columns(rpid_ctx ctx, int64_t k, int64_t n, const int64_t* J, double* Z, int64_t ldz) {
+  hipLaunchKernelGGL(identity_cols_kernel, dim3(grid_for(k * k)), dim3(256), 0, ctx->stream, k, n, J,
                      Z, ldz);
   RPID_HIP_CHECK(hipGetLastError());
   return RPID_OK;

@@ -62,6 +62,7 @@ _SIGS = {
     "rpid_id_coeffs_ls": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I]),
     "rpid_sketch_fp8": (_i, [_P, _P, _I, _I, _I, _P, _I, _I, _P, _I]),
     "rpid_select_columns": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, ctypes.POINTER(_I)]),
+    "rpid_select_columns_async": (_i, [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, _P]),
     "rpid_id_coeffs": (
         _i,
         [_P, _P, _i, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, _I, _i, ctypes.POINTER(ctypes.c_double)],
@@ -279,6 +280,23 @@ def rpid_select_columns(ctx: Context, X: torch.Tensor, k: int, sync: bool = True
     )
     _check("rpid_select_columns", s, allow_positive=True)
     return J, Lf, Uf, diag, (keff.value if sync else None), (s if sync else None)
+
+
+def rpid_select_columns_async(ctx: Context, X: torch.Tensor, k: int):
+    """rpid_select_columns without the host read: returns (J, Lf, Uf, diagU,
+    status) with status a device int64 tensor of one element (0, t + 1 for
+    an exactly zero pivot at step t, or a negative RPID_ERR_* code), written
+    in stream order."""
+    px, l, n, ldx = colmajor(X)
+    J = torch.empty(k, dtype=torch.int64, device=X.device)
+    Lf = empty_colmajor(n, k, X.dtype, X.device)
+    Uf = empty_colmajor(k, k, X.dtype, X.device)
+    diag = torch.empty(k, dtype=X.dtype, device=X.device)
+    status = torch.empty(1, dtype=torch.int64, device=X.device)
+    _check("rpid_select_columns_async", lib().rpid_select_columns_async(
+        ctx.handle, px, dtype_code(X), l, n, ldx, k, J.data_ptr(), Lf.data_ptr(), Lf.stride(1),
+        Uf.data_ptr(), Uf.stride(1), diag.data_ptr(), status.data_ptr()))
+    return J, Lf, Uf, diag, status
 
 
 def rpid_sketch_sparse_sign(ctx: Context, A: torch.Tensor, rows: torch.Tensor, signs: torch.Tensor, l: int,
@@ -574,6 +592,10 @@ def decompose_overlapped(ctx, ctx2, A, Omega, k, refine_steps=None):
     X = rpid_sketch(ctx, A, Omega)
     if refine_steps is None:
         refine_steps = 0 if X.dtype == torch.float64 else 1
+    # the pivots' status is read before the branches are enqueued: with it
+    # left on the device (rpid_select_columns_async) the side branch's first
+    # kernels reach the compute units together with the row LUPP, whose
+    # cooperative launch then waits for them (measured slower)
     J, Lf, Uf, diag, keff, st = rpid_select_columns(ctx, X, k)
     out = dict(X=X, J=J, Lf=Lf, Uf=Uf, diag=diag, k_eff=keff, status=st)
     if st != 0:

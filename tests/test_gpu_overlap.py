@@ -67,3 +67,66 @@ def test_residual_sums_match_residual():
             assert math.sqrt(s0 / s1) == r
     finally:
         ctx.close()
+
+
+def test_overlapped_zero_pivot_reports_status():
+    """A matrix with only 20 nonzero columns and k = 32: the column LUPP meets
+    an exactly zero pivot at step 20.  The overlapped step reports the
+    sequential call's status and first 20 pivots and returns no
+    decomposition; rpid_select_columns_async gives the same pivots and factors
+    as rpid_select_columns with the status in a device word, and the work
+    enqueued on its J before that word is read (CUR, Z, both residuals, with
+    J past step 20 never written) runs to completion without touching memory
+    outside its buffers."""
+    from paper_2104_05877_amd import rpid as R
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    print("[overlap] zero pivot", flush=True)
+    m, n, k, l, r = 1024, 768, 32, 40, 20
+    rng = np.random.default_rng(41)
+    A = np.zeros((m, n))
+    cols = rng.choice(n, r, replace=False)
+    A[:, cols] = rng.standard_normal((m, r))
+    Om = rng.standard_normal((l, m))
+    Ad = inputs.torch_colmajor(A, torch.float64, "cuda")
+    Od = inputs.torch_colmajor(Om, torch.float64, "cuda")
+    ctx = R.Context(0)
+    ctx2 = R.Context(0, stream=torch.cuda.Stream(device=0))
+    try:
+        seq = R.decompose(ctx, Ad, Od, k)
+        assert seq["status"] == r + 1 and seq["k_eff"] == r
+        for _ in range(2):
+            ov = R.decompose_overlapped(ctx, ctx2, Ad, Od, k)
+            assert ov["status"] == r + 1 and ov["k_eff"] == r
+            assert torch.equal(ov["J"][:r], seq["J"][:r])
+            assert "Z" not in ov and "U" not in ov
+        # the asynchronous pivots, and dependent work on them, before the status is read
+        for dt in (torch.float64, torch.float32):
+            X = R.rpid_sketch(ctx, Ad.to(dt), Od.to(dt))
+            Js, Ls, Us, ds, ke, st = R.rpid_select_columns(ctx, X, k)
+            Ja, La, Ua, da, st_dev = R.rpid_select_columns_async(ctx, X, k)
+            # J past step 20 is unwritten: breakdown statuses from the garbage
+            # are expected, faults are not
+            try:
+                I, U, ke_i, st_i = R.rpid_cur(ctx, Ad, k, Ja)
+                R.rpid_residual_sums(ctx, R.RESIDUAL_CUR, Ad, k, Ja, I=I, U=U)
+            except R.RpidError:
+                pass
+            try:
+                Z, _ = R.rpid_id_coeffs(ctx, X, k, Ja, La, Ua)
+                R.rpid_residual_sums(ctx, R.RESIDUAL_ID, Ad, k, Ja, Z=Z)
+            except R.RpidError:
+                pass
+            torch.cuda.synchronize()
+            assert int(st_dev.item()) == st == r + 1
+            assert torch.equal(Ja[:r], Js[:r]) and torch.equal(La[:, :r], Ls[:, :r])
+            assert torch.equal(Ua[:r, :r], Us[:r, :r])
+        # the contexts still work afterwards
+        A2, Om2 = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 42)
+        ok = R.decompose_overlapped(ctx, ctx2, inputs.torch_colmajor(A2, torch.float64, "cuda"),
+                                    inputs.torch_colmajor(Om2, torch.float64, "cuda"), k)
+        assert ok["status"] == 0 and np.isfinite(ok["residual_id"]) and np.isfinite(ok["residual_cur"])
+    finally:
+        ctx2.close()
+        ctx.close()
