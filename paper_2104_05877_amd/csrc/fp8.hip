@@ -309,6 +309,44 @@ __global__ __launch_bounds__(256) void omega_max_kernel(const float* Om, int64_t
   if (threadIdx.x == 0) part[blockIdx.x] = mx;
 }
 
+// the same partial maxima for a contiguous Omega (ldo == l): the l m values
+// as one array, four per 16-byte load, four loads in flight per thread
+__global__ __launch_bounds__(256) void omega_max_flat_kernel(const float* Om, int64_t total,
+                                                             float* part) {
+  __shared__ float red[4];
+  float mx = 0.0f;
+  auto take = [&](float x) {
+    const float a = fabsf(x);
+    mx = (a == a) ? fmaxf(mx, a) : INFINITY;
+  };
+  const int64_t n4 = total / 4;
+  const float4* O4 = reinterpret_cast<const float4*>(Om);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    float4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = O4[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      take(v[u].x);
+      take(v[u].y);
+      take(v[u].z);
+      take(v[u].w);
+    }
+  }
+  for (; i < n4; i += stride) {
+    const float4 v = O4[i];
+    take(v.x);
+    take(v.y);
+    take(v.z);
+    take(v.w);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < total - 4 * n4) take(Om[4 * n4 + threadIdx.x]);
+  mx = block_max(mx, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
 // eo from the partial maxima (one workgroup)
 __global__ __launch_bounds__(256) void omega_scale_kernel(const float* part, int nparts, int* eo) {
   __shared__ float red[4];
@@ -404,7 +442,10 @@ int sketch_fp8(rpid_ctx ctx, const float* A, int64_t m, int64_t n, int64_t lda, 
   RPID_HIP_CHECK(hipGetLastError());
   // at least eight columns of Omega per workgroup (two rounds of its four waves)
   const int parts = (int)std::min<int64_t>(OMAX_PARTS, (m + 7) / 8);
-  hipLaunchKernelGGL(omega_max_kernel, dim3(parts), dim3(256), 0, ctx->stream, Om, l, m, ldo, part);
+  if (ldo == l && reinterpret_cast<uintptr_t>(Om) % 16 == 0)
+    hipLaunchKernelGGL(omega_max_flat_kernel, dim3(parts), dim3(256), 0, ctx->stream, Om, l * m, part);
+  else
+    hipLaunchKernelGGL(omega_max_kernel, dim3(parts), dim3(256), 0, ctx->stream, Om, l, m, ldo, part);
   RPID_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(omega_scale_kernel, dim3(1), dim3(256), 0, ctx->stream, part, parts, eo);
   RPID_HIP_CHECK(hipGetLastError());

@@ -268,6 +268,52 @@ def test_fp8_codes_scaled_columns_exact(R, ctx, m, n, l):
     assert np.array_equal(X, O.sketch_fp8(A, Om))
 
 
+def test_fp8_contiguous_and_strided_paths_agree(R, ctx):
+    """The FP8 sketch through its contiguous kernels (16-byte loads of whole
+    2048-row groups of A, the flat maximum of Omega) and through its general
+    ones (A and Omega as strided views, leading dimensions rows + 1): X
+    bitwise equal, finite input or not.  A non-finite entry of A gives a NaN
+    column of X (that column unscaled), a NaN in Omega a NaN row (Omega
+    unscaled); the other columns keep the finite case's values bit for bit."""
+    m, n, l = 4096, 40, 48
+    say("fp8 paths", m, n, l)
+    rng = np.random.default_rng(23)
+    A0 = (rng.standard_normal((m, n)) * 10.0 ** rng.uniform(-3, 3, n)[None, :]).astype(np.float32)
+    Om0 = rng.standard_normal((l, m)).astype(np.float32)
+
+    def strided(M):
+        r, c = M.shape
+        buf = torch.zeros((c, r + 1), dtype=torch.float32, device="cuda")
+        buf[:, :r] = torch.from_numpy(np.ascontiguousarray(M.T)).cuda()
+        return buf[:, :r].T
+
+    X_fin = None
+    for case in ("finite", "A_nonfinite", "Om_nan"):
+        A, Om = A0.copy(), Om0.copy()
+        if case == "A_nonfinite":
+            A[5, 3], A[7, 9] = np.nan, np.inf
+        if case == "Om_nan":
+            Om[2, 100] = np.nan
+        Ac = inputs.torch_colmajor(A, torch.float32, "cuda")
+        Oc = inputs.torch_colmajor(Om, torch.float32, "cuda")
+        As, Os = strided(A), strided(Om)
+        assert As.stride() == (1, m + 1) and Os.stride() == (1, l + 1)
+        X1 = host(R.rpid_sketch_fp8(ctx, Ac, Oc))
+        X2 = host(R.rpid_sketch_fp8(ctx, As, Os))
+        assert np.array_equal(X1, X2, equal_nan=True), case
+        if case == "finite":
+            assert np.all(np.isfinite(X1))
+            X_fin = X1
+        elif case == "A_nonfinite":
+            bad = np.zeros(n, dtype=bool)
+            bad[[3, 9]] = True
+            assert np.all(np.isnan(X1[:, bad]))
+            assert np.array_equal(X1[:, ~bad], X_fin[:, ~bad])
+        else:
+            assert np.all(np.isnan(X1[2, :]))
+            assert np.all(np.isfinite(np.delete(X1, 2, axis=0)))
+
+
 def test_lupp_grid_above_one_workgroup_per_cu_refused(R, ctx):
     """A panel that would need more workgroups than compute units (FP64, k =
     384, 65536 rows: 128 rows per workgroup at most) is refused on the host
