@@ -269,6 +269,39 @@ def test_large_k_f64_end_to_end(R, ctx, m, n, k, l, seed):
     assert abs(rcur - ro["cur"]) <= 1e-9 * ro["cur"]
 
 
+@pytest.mark.parametrize("m,n,k,l,seed", [(5, 7, 1, 1, 1), (33, 40, 1, 3, 2), (64, 31, 31, 31, 3),
+                                          (9, 300, 9, 9, 4), (130, 97, 97, 100, 5)])
+def test_degenerate_ranks_f64_end_to_end(R, ctx, m, n, k, l, seed):
+    """The extreme ranks of Alg. 2: k = 1 (one sketch row, one pivot, 1 x 1
+    triangular factors), k = n (every column is a pivot, Z a permutation of
+    the identity) and k = m (the row LUPP of C takes every row), with m, n
+    and l below one tile.  J and I bit-exact, Z and U within their
+    conditioning; residuals to 1e-9 relative, or at round-off where the
+    oracle's are (the selected columns or rows then span A)."""
+    say("degenerate ranks f64", m, n, k, l)
+    A, Om = inputs.small_spectral_case(m, n, k, l, np.linspace(1.0, 0.5, min(m, n)), 60 + seed)
+    o = O.decompose(A, Om, k, gaps=True)
+    assert o["gap_J"].min() > 1e-6 and o["gap_I"].min() > 1e-6
+    Ad, Od = dev(A), dev(Om)
+    g = R.decompose(ctx, Ad, Od, k)
+    assert g["status"] == 0 and g["status_I"] == 0
+    assert np.array_equal(host(g["J"]).astype(np.int64), o["J"])
+    assert np.array_equal(host(g["I"]).astype(np.int64), o["I"])
+    kappa = np.linalg.cond(o["X"][:k][:, o["J"]])
+    np.testing.assert_allclose(host(g["Z"]), o["Z"], rtol=0,
+                               atol=1e-13 * kappa * max(1.0, np.abs(o["Z"]).max()))
+    np.testing.assert_allclose(host(g["U"]), o["U"], rtol=1e-7, atol=1e-7 * np.abs(o["U"]).max())
+    ro = O.residuals(A, o["J"], Z=o["Z"], I=o["I"], U=o["U"], only=("id", "cur"))
+    rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, g["J"], Z=g["Z"])
+    rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, k, g["J"], I=g["I"], U=g["U"])
+    say("residuals gpu", rid, rcur, "oracle", ro["id"], ro["cur"])
+    for rg, r in ((rid, ro["id"]), (rcur, ro["cur"])):
+        if r > 1e-10:
+            assert abs(rg - r) <= 1e-9 * r
+        else:
+            assert rg <= 1e-12
+
+
 @pytest.mark.parametrize("m,n,k,seed", [(2600, 2200, 600, 11), (2100, 2300, 1024, 12)])
 def test_id_beyond_512_f64(R, ctx, m, n, k, seed):
     """The interpolative decomposition at ranks above 512 (the triangular
