@@ -48,8 +48,10 @@ def first_close(gap, thr):
 
 
 # (l, n, k, seed): one workgroup column block of 16 or 32 columns, 256 or 512
-# threads, ragged n, k up to l = 512
-SHAPES = [(16, 100, 10, 1), (64, 1000, 64, 2), (300, 5000, 200, 3), (512, 2048, 512, 4), (272, 8192, 256, 5)]
+# threads, ragged n, k up to l = 512; then the extreme ranks: one sketch row
+# (k = l = 1, a reflector of length one), k = 1 of three rows, k = l = n
+SHAPES = [(16, 100, 10, 1), (64, 1000, 64, 2), (300, 5000, 200, 3), (512, 2048, 512, 4), (272, 8192, 256, 5),
+          (1, 7, 1, 11), (3, 40, 1, 13), (31, 31, 31, 12)]
 
 
 @pytest.mark.parametrize("l,n,k,seed", SHAPES)

@@ -89,15 +89,7 @@ def test_two_sided_sketch_against_oracle(R, ctx, m, n, l, pad, seed, dt):
     assert np.all(ex <= bx) and np.all(ey <= by)
 
 
-def test_two_sided_fp64_decomposition(R, ctx):
-    """FP64 end to end: J from X and I from Y equal the oracle's (no near-ties
-    on this input), the row ID from Y (rpid_id_coeffs on Y^T) and the cheap
-    core S^{-1} match the oracle's within their conditioning, and the row ID
-    and cheap CUR residuals match to 1e-9 relative."""
-    m, n, k, l = 1200, 1000, 40, 48
-    A, _ = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 11)
-    rng = np.random.default_rng(12)
-    G, Om = rng.standard_normal((l, m)), rng.standard_normal((l, n))
+def _two_sided_fp64_case(R, ctx, A, G, Om, k):
     Ad = dev(A, torch.float64)
     X, Yt = R.rpid_sketch_two_sided(ctx, Ad, dev(G, torch.float64), dev(Om, torch.float64))
     o = O.decompose_two_sided(A, G, Om, k, gaps=True)
@@ -118,8 +110,35 @@ def test_two_sided_fp64_decomposition(R, ctx):
     r_cur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, k, J, I=I, U=Us)
     ro = O.residuals(A, o["J"], I=o["I"], U=o["U_sketch"], W=o["W"], only=("rowid", "cur"))
     say("row id", r_row, ro["rowid"], "cheap cur", r_cur, ro["cur"])
-    assert abs(r_row - ro["rowid"]) <= 1e-9 * ro["rowid"]
-    assert abs(r_cur - ro["cur"]) <= 1e-9 * ro["cur"]
+    for rg, r in ((r_row, ro["rowid"]), (r_cur, ro["cur"])):
+        if r > 1e-10:
+            assert abs(rg - r) <= 1e-9 * r
+        else:  # the selected rows or columns span A: round-off
+            assert rg <= 1e-12
+
+
+def test_two_sided_fp64_decomposition(R, ctx):
+    """FP64 end to end: J from X and I from Y equal the oracle's (no near-ties
+    on this input), the row ID from Y (rpid_id_coeffs on Y^T) and the cheap
+    core S^{-1} match the oracle's within their conditioning, and the row ID
+    and cheap CUR residuals match to 1e-9 relative."""
+    m, n, k, l = 1200, 1000, 40, 48
+    A, _ = inputs.small_spectral_case(m, n, k, l, inputs.poly_spectrum(min(m, n), 2.0), 11)
+    rng = np.random.default_rng(12)
+    G, Om = rng.standard_normal((l, m)), rng.standard_normal((l, n))
+    _two_sided_fp64_case(R, ctx, A, G, Om, k)
+
+
+@pytest.mark.parametrize("m,n,k,l,seed", [(7, 5, 1, 1, 1), (40, 33, 33, 33, 2), (30, 50, 30, 30, 3)])
+def test_two_sided_fp64_extreme_ranks(R, ctx, m, n, k, l, seed):
+    """Alg. 3 at k = 1 with one sketch row on each side, at k = n (every
+    column a pivot) and at k = m (every row a pivot): the same checks, with
+    the residuals at round-off where the pivots span A."""
+    say("two-sided extreme ranks", m, n, k, l)
+    A, _ = inputs.small_spectral_case(m, n, k, l, np.linspace(1.0, 0.5, min(m, n)), 70 + seed)
+    rng = np.random.default_rng(80 + seed)
+    G, Om = rng.standard_normal((l, m)), rng.standard_normal((l, n))
+    _two_sided_fp64_case(R, ctx, A, G, Om, k)
 
 
 @pytest.mark.parametrize("m,n,k,l", [(2048, 1536, 64, 80), (4096, 4096, 128, 144)])
