@@ -208,6 +208,35 @@ def test_poly8192_bf16(R, ctx, poly8192):
     _low_precision_mode(R, ctx, Ab, Ob, A, Om, o, "bf16")
 
 
+@pytest.mark.parametrize("dt", ["float64", "bfloat16"])
+def test_poly8192_overlapped_step_equals_sequential(R, ctx, poly8192, dt):
+    """The step as the benchmark times it (Z and the ID residual on a second
+    context and stream, beside the CUR step and its residual) at the
+    benchmark size: bitwise the J, I, Z and U of the sequential order checked
+    against the oracle above, and the residuals of rpid_residual, on every
+    repetition."""
+    a32, om32 = poly8192
+    tdt = getattr(torch, dt)
+    Ad = a32.T.contiguous().to(tdt).T
+    Od = om32.T.contiguous().to(tdt).T
+    say("overlapped step", dt, M, N, K, L)
+    ctx2 = R.Context(0, stream=torch.cuda.Stream(device=0))
+    try:
+        seq = R.decompose(ctx, Ad, Od, K)
+        assert seq["status"] == 0 and seq["status_I"] == 0
+        rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, K, seq["J"], Z=seq["Z"])
+        rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, K, seq["J"], I=seq["I"], U=seq["U"])
+        for _ in range(3):
+            ov = R.decompose_overlapped(ctx, ctx2, Ad, Od, K)
+            assert ov["status"] == 0 and ov["status_I"] == 0
+            assert torch.equal(ov["J"], seq["J"]) and torch.equal(ov["I"], seq["I"])
+            assert torch.equal(ov["Z"], seq["Z"]) and torch.equal(ov["U"], seq["U"])
+            assert ov["residual_id"] == rid and ov["residual_cur"] == rcur
+        say("residuals", rid, rcur)
+    finally:
+        ctx2.close()
+
+
 def test_lowrank16384_bf16_k512(R, ctx):
     """The BF16 precision form at its own size: 16384 x 16384 stored BF16,
     k = 512, l = 544.  FP32 LUPPs bit-exact against the fixed-arithmetic
