@@ -535,6 +535,7 @@ class _SideWorker:
         self._done = threading.Event()
         self._job = None
         self._out = None
+        self._pending = False  # a job started and its result not yet taken
         self._thread = threading.Thread(target=self._loop, daemon=True)
         self._thread.start()
 
@@ -553,11 +554,13 @@ class _SideWorker:
 
     def start(self, job):
         self._job = job
+        self._pending = True
         self._done.clear()
         self._go.set()
 
     def result(self):
         self._done.wait()
+        self._pending = False
         out, err = self._out
         self._out = None
         if err is not None:
@@ -565,6 +568,10 @@ class _SideWorker:
         return out
 
     def stop(self):
+        # a job already handed over runs to its end first: clearing it before
+        # the thread has picked it up would drop it and leave result() waiting
+        if self._pending:
+            self._done.wait(timeout=60.0)
         self._job = None
         self._go.set()
         self._thread.join(timeout=5.0)

@@ -61,6 +61,26 @@ def test_worker_reraises_in_the_caller_and_keeps_serving():
     assert not w._thread.is_alive()
 
 
+def test_stop_lets_a_started_job_finish():
+    """stop() right after start(), before the result is taken: the job still
+    runs to its end, its result stays available, and the thread ends."""
+    w = R._SideWorker()
+    release, ran = threading.Event(), []
+
+    def job():
+        assert release.wait(timeout=10.0)
+        ran.append(True)
+        return 5
+
+    w.start(job)
+    timer = threading.Timer(0.2, release.set)
+    timer.start()
+    w.stop()
+    timer.join()
+    assert ran == [True] and w.result() == 5
+    assert not w._thread.is_alive()
+
+
 def test_relative_residual_from_sums():
     assert R._relative(torch.tensor([4.0, 16.0], dtype=torch.float64)) == 0.5
     assert R._relative(torch.tensor([0.0, 9.0], dtype=torch.float64)) == 0.0
