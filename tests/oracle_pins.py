@@ -675,3 +675,49 @@ def pin_id_coeffs_ls(O, seed=58, l=14, n=40, k=9):
 
 
 ALL_PINS += [pin_id_coeffs_ls]
+
+
+def pin_extreme_ranks(O, seed=60):
+    """Alg. 2 at its extreme ranks, where the results have closed forms.
+    k = 1 with one sketch row: the pivot is the entry of largest magnitude
+    (the smallest index among equals), Z is that row divided by its pivot
+    entry, and the row pivot is the largest |C(i, 0)|.  k = n: every column
+    is a pivot, Z is the permutation matrix with Z(i, J(i)) = 1, so C Z = A
+    exactly, and C U R = A up to round-off.  k = m: every row is a pivot of
+    C, and A = C Z up to round-off (X(:, J) is then square and invertible)."""
+    rng = np.random.default_rng(seed)
+    # k = 1, l = 1, with a tie for the largest magnitude
+    m, n = 9, 8
+    a = rng.standard_normal((m, n))
+    om = rng.standard_normal((1, m))
+    x = om @ a
+    j_max = int(np.argmax(np.abs(x[0])))
+    a[:, n - 1] = -a[:, j_max]  # the same magnitude at a later index
+    d = O.decompose(a, om, 1)
+    x = O.sketch(a, om)
+    assert d["J"][0] == int(np.argmax(np.abs(x[0]))) == j_max
+    np.testing.assert_allclose(d["Z"][0], x[0] / x[0, j_max], rtol=1e-15, atol=0)
+    assert d["I"][0] == int(np.argmax(np.abs(a[:, j_max])))
+    # k = n
+    m, n = 12, 7
+    a = rng.standard_normal((m, n))
+    om = rng.standard_normal((n, m))
+    d = O.decompose(a, om, n)
+    assert sorted(d["J"]) == list(range(n))
+    P = np.zeros((n, n))
+    P[np.arange(n), d["J"]] = 1.0
+    assert np.array_equal(d["Z"], P)
+    assert O.eta(d["Z"], d["J"]) == 1.0
+    r = O.residuals(a, d["J"], Z=d["Z"], I=d["I"], U=d["U"], only=("id", "cur"))
+    assert r["id"] == 0.0 and r["cur"] < 1e-13, r
+    # k = m
+    m, n = 6, 15
+    a = rng.standard_normal((m, n))
+    om = rng.standard_normal((m, m))
+    d = O.decompose(a, om, m)
+    assert sorted(d["I"]) == list(range(m))
+    r = O.residuals(a, d["J"], Z=d["Z"], I=d["I"], U=d["U"], only=("id", "cur"))
+    assert r["id"] < 1e-12 and r["cur"] < 1e-12, r
+
+
+ALL_PINS += [pin_extreme_ranks]
