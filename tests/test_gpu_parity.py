@@ -365,6 +365,36 @@ def test_precision_modes_small(R, ctx, dt):
     assert abs(rcur - rg["cur"]) <= 1e-4 * rg["cur"]
 
 
+@pytest.mark.parametrize("dt", ["float32", "bfloat16"])
+@pytest.mark.parametrize("m,n,k,l", [(300, 257, 1, 1), (64, 31, 31, 31)])
+def test_precision_modes_extreme_ranks(R, ctx, dt, m, n, k, l):
+    """FP32 and BF16 storage at k = 1 (one sketch row; in BF16 the CUR's
+    product W = Q_C^T A runs on two sketch rows) and at k = n.  k = 1: both
+    residuals within 1.05x of the FP64 oracle's on the same stored values.
+    k = n: Z is a permutation, so A - CZ vanishes exactly; the CUR residual
+    stays at the precision of W's product (FP32: 2^-24; BF16: Q_C in two BF16
+    terms, about 2^-16), bounded here by 1e-5 and 1e-3."""
+    say("precision extreme ranks", dt, m, n, k, l)
+    tdt = getattr(torch, dt)
+    A, Om = inputs.small_spectral_case(m, n, k, l, np.linspace(1.0, 0.5, min(m, n)), 90 + k)
+    Ad, Od = dev(A, tdt), dev(Om, tdt)
+    g = R.decompose(ctx, Ad, Od, k)
+    assert g["status"] == 0 and g["status_I"] == 0
+    rid = R.rpid_residual(ctx, R.RESIDUAL_ID, Ad, k, g["J"], Z=g["Z"])
+    rcur = R.rpid_residual(ctx, R.RESIDUAL_CUR, Ad, k, g["J"], I=g["I"], U=g["U"])
+    if k == n:
+        say("gpu", rid, rcur)
+        assert sorted(host(g["J"]).astype(np.int64).tolist()) == list(range(n))
+        assert rid == 0.0
+        assert rcur <= (1e-5 if dt == "float32" else 1e-3)
+    else:
+        a_s, o_s = host(Ad), host(Od)
+        o = O.decompose(a_s, o_s, k)
+        ro = O.residuals(a_s, o["J"], Z=o["Z"], I=o["I"], U=o["U"], only=("id", "cur"))
+        say("gpu", rid, rcur, "oracle", ro["id"], ro["cur"])
+        assert rid <= 1.05 * ro["id"] and rcur <= 1.05 * ro["cur"]
+
+
 def test_argument_validation(R, ctx):
     """Invalid arguments return -position; nothing is launched."""
     say("validation")
