@@ -837,7 +837,7 @@ def main():
         summarize_counters(*args.summarize_counters, args.mode)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the path runs on one GPU (how it would shard is described, not run); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
