@@ -623,8 +623,12 @@ def decompose_overlapped(ctx, ctx2, A, Omega, k, refine_steps=None):
         I, U, keff_i, st_i = rpid_cur(ctx, A, k, J)
         scur = rpid_residual_sums(ctx, RESIDUAL_CUR, A, k, J, I=I, U=U) if st_i == 0 else None
     finally:
-        Z, sid = worker.result()
-    ctx2.stream.synchronize()
+        # also when the CUR branch raised: the side stream may still be
+        # writing Z and its sums, which must not be freed before it is done
+        try:
+            Z, sid = worker.result()
+        finally:
+            ctx2.stream.synchronize()
     ctx.stream.synchronize()
     out.update(Z=Z, I=I, U=U, status_I=st_i, residual_id=_relative(sid),
                residual_cur=_relative(scur) if scur is not None else None)
