@@ -5,8 +5,12 @@ torch tensors on the GPU in column-major layout: an m x n matrix is a tensor
 ``t`` of shape (m, n) with ``t.stride() == (1, ld)``, ``ld >= m`` (e.g. the
 transpose of a contiguous (n, m) tensor).  Index vectors are int64 tensors.
 All calls enqueue on the stream given to :class:`Context` (by default torch's
-current stream).  There is no fallback: if the HIP library is missing or the
-GPU is absent, the calls raise.
+current stream).  Outputs are allocated by torch on its current stream: with a
+context on another stream, keep them alive until that stream has been
+synchronised (or mark them with ``Tensor.record_stream``), or torch may hand
+their memory out again while the context's kernels still write it.  There is
+no fallback: if the HIP library is missing or the GPU is absent, the calls
+raise.
 """
 from __future__ import annotations
 
